@@ -1,0 +1,242 @@
+"""Pins for the FP64 oracle: checks against facts the paper and mathematics fix.
+
+Each pin takes an oracle handle (``oracle.default()`` or a test build) and
+raises AssertionError when the oracle disagrees. None of them retypes the
+oracle's own formula: they use exact rational arithmetic, closed forms,
+symmetries, and the numbers printed in the paper.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction as F
+
+import numpy as np
+
+import exact_ref
+from paper_1005_5198_amd import workloads as w
+
+
+def _p(sigma_c, gamma, shoot, src, window=None):
+    return w.make_params(0.0, sigma_c, gamma, shoot, src, window)
+
+
+NO_LENS = np.zeros((0, 2))
+
+
+# ---------------------------------------------------------------------------
+# Pin 1: identity. No lenses, no shear, no convergence (Section 2, Eq. (mu_ij):
+# without lensing every pixel receives exactly N_rays; Section 3.1 regular grid).
+# ---------------------------------------------------------------------------
+def pin_identity(orc):
+    p = _p(0.0, 0.0, (-20.0, -20.0, 40.0, 40.0, 1024, 1024), (-10.0, -10.0, 20.0, 20.0, 256, 256))
+    m, st = orc.make_map(p, NO_LENS)
+    assert np.all(m == 4), f"identity map not all 4: min {m.min()} max {m.max()}"
+    assert st["rays_out"] == 1024 * 1024 - 4 * 256 * 256, st
+    assert st["rays_singular"] == 0
+    # pixel = 3 ray spacings: 9 per pixel
+    p = _p(0.0, 0.0, (-12.0, -12.0, 24.0, 24.0, 96, 96), (-6.0, -6.0, 12.0, 12.0, 16, 16))
+    m, st = orc.make_map(p, NO_LENS)
+    assert np.all(m == 9), "identity with pix = 3 spacings"
+    assert st["rays_out"] == 96 * 96 - 9 * 256
+
+
+# ---------------------------------------------------------------------------
+# Pin 2: pure convergence and shear (sigma_* = 0). The map is separable:
+# map[q][p] = c2[q] * c1[p], each factor a 1-D lattice count done in exact
+# rationals. Dyadic parameters make the FP64 evaluation exact, so equality
+# is exact, including rays that sit exactly on pixel edges.
+# ---------------------------------------------------------------------------
+def _separable_case(orc, sigma_c, gamma, shoot, src):
+    p = _p(sigma_c, gamma, shoot, src)
+    m, st = orc.make_map(p, NO_LENS)
+    a1 = 1 - F(gamma) - F(sigma_c)
+    a2 = 1 + F(gamma) - F(sigma_c)
+    c1, _ = exact_ref.lattice_count_1d(a1, F(shoot[0]), F(shoot[2]), shoot[4], F(src[0]), F(src[2]), src[4])
+    c2, _ = exact_ref.lattice_count_1d(a2, F(shoot[1]), F(shoot[3]), shoot[5], F(src[1]), F(src[3]), src[5])
+    expect = np.outer(np.array(c2, dtype=np.int64), np.array(c1, dtype=np.int64))
+    assert m.shape == expect.shape
+    assert np.array_equal(m.astype(np.int64), expect), \
+        f"separable lattice mismatch at sigma_c={sigma_c} gamma={gamma}: {int(np.abs(m - expect).sum())}"
+    total = shoot[4] * shoot[5]
+    assert st["rays_out"] == total - int(expect.sum())
+
+
+def pin_separable(orc):
+    # generic dyadic shear and convergence; some rays land outside the map
+    _separable_case(orc, 0.125, 0.25, (-20.0, -10.0, 40.0, 20.0, 320, 160), (-10.0, -10.0, 20.0, 20.0, 80, 80))
+    # negative parity along x1 (1 - gamma - sigma_c < 0)
+    _separable_case(orc, 0.75, 0.5, (-48.0, -16.0, 96.0, 32.0, 384, 256), (-10.0, -10.0, 20.0, 20.0, 40, 40))
+    # rays exactly on pixel edges (half-open convention, including u = 0 and u = npx)
+    _separable_case(orc, 0.0, 0.0, (-8.0, -4.0, 16.0, 8.0, 64, 32), (-7.875, -3.875, 8.0, 4.0, 32, 16))
+    # non-square grids, different spacings per axis
+    _separable_case(orc, 0.25, 0.125, (-20.0, -12.0, 40.0, 24.0, 160, 384), (-9.0, -11.0, 18.0, 22.0, 36, 44))
+
+
+# ---------------------------------------------------------------------------
+# Pin 2b: the mean magnification of the macro model, Eq. (mutheory),
+# mu_av = 1 / ((1-sigma)^2 - gamma^2); |mu_av| is the mean count ratio.
+# ---------------------------------------------------------------------------
+def pin_mean_mu(orc):
+    for sigma_c, gamma in ((0.3, 0.2), (0.1, 0.45), (0.55, 0.1)):
+        a1 = 1.0 - sigma_c - gamma
+        a2 = 1.0 - sigma_c + gamma
+        spacing = 0.05
+        w1 = 1.3 * 20.0 / abs(a1)
+        w2 = 1.3 * 20.0 / abs(a2)
+        nx = int(round(w1 / spacing))
+        ny = int(round(w2 / spacing))
+        p = _p(sigma_c, gamma, (-nx * spacing / 2, -ny * spacing / 2, nx * spacing, ny * spacing, nx, ny),
+               (-10.0, -10.0, 20.0, 20.0, 64, 64))
+        m, _ = orc.make_map(p, NO_LENS)
+        n_rays = (20.0 / 64 / spacing) ** 2
+        mean_mu = m.sum() / (64 * 64 * n_rays)
+        mu = 1.0 / ((1.0 - sigma_c) ** 2 - gamma ** 2)
+        assert abs(mean_mu - abs(mu)) < 0.01 * abs(mu), (sigma_c, gamma, mean_mu, mu)
+
+
+# ---------------------------------------------------------------------------
+# Pin 3: a single point lens (m=1 at the origin, sigma_c = gamma = 0).
+# The lens equation is radial: |y| = |r - 1/r|. Rays with |y| < U are exactly
+# those with x-(U) < r < x+(U), x+- = (sqrt(U^2+4) +- U)/2, and that image
+# area is pi U sqrt(U^2+4). Annulus-averaged magnification matches the
+# textbook mu(u) = (u^2+2)/(u sqrt(u^2+4)).
+# ---------------------------------------------------------------------------
+def pin_point_lens(orc, n=600, half=3.0):
+    spacing = 2 * half / n
+    pix = 1.0 / 64
+    p = _p(0.0, 0.0, (-half, -half, 2 * half, 2 * half, n, n), (-4.0, -4.0, 8.0, 8.0, 512, 512))
+    lens = np.array([[0.0, 0.0]])
+    pix_id, u, v = orc.ray_pixels(p, lens)
+    y1 = u * pix - 4.0
+    y2 = v * pix - 4.0
+    ymag = np.hypot(y1, y2)
+    xs = -half + (np.arange(n) + 0.5) * spacing
+    X1, X2 = np.meshgrid(xs, xs)
+    r = np.hypot(X1, X2).reshape(-1)
+    counts = []
+    for U in (0.25, 0.5, 1.0, 1.5, 2.0):
+        xp = (math.sqrt(U * U + 4) + U) / 2
+        xm = (math.sqrt(U * U + 4) - U) / 2
+        ok = (np.abs(ymag - U) > 1e-9) & (np.abs(r - xp) > 1e-9) & (np.abs(r - xm) > 1e-9)
+        ok &= np.isfinite(ymag)
+        by_map = np.count_nonzero((ymag < U) & ok)
+        by_preimage = np.count_nonzero((r > xm) & (r < xp) & ok)
+        assert by_map == by_preimage, (U, by_map, by_preimage)
+        area = by_map * spacing * spacing
+        closed = math.pi * U * math.sqrt(U * U + 4)
+        # lattice error is bounded by the boundary length times one spacing
+        tol = 2 * math.pi * (xp + xm) * spacing * 1.5 + 4 * spacing * spacing
+        assert abs(area - closed) < tol, (U, area, closed)
+        counts.append((U, by_map))
+    # annulus-averaged magnification vs the analytic mu(u), integrated numerically
+    from scipy.integrate import quad
+
+    def mu(s):
+        return (s * s + 2) / (s * math.sqrt(s * s + 4))
+
+    for (ua, ca), (ub, cb) in zip(counts, counts[1:]):
+        mean_mu = (cb - ca) * spacing * spacing / (math.pi * (ub * ub - ua * ua))
+        analytic = quad(lambda s: mu(s) * 2 * math.pi * s, ua, ub)[0] / (math.pi * (ub * ub - ua * ua))
+        assert abs(mean_mu - analytic) < 0.03 * analytic, (ua, ub, mean_mu, analytic)
+
+
+# ---------------------------------------------------------------------------
+# Pin 4: the sign of gamma swaps the axes. Reflecting everything across the
+# diagonal (x1 <-> x2, all grid parameters swapped) and flipping gamma gives
+# the transposed map, bit for bit (the arithmetic is the same, operands swapped).
+# ---------------------------------------------------------------------------
+def pin_gamma_transpose(orc, seed=11):
+    rng = np.random.default_rng(seed)
+    lens = rng.uniform(-9, 9, size=(37, 2))
+    masses = rng.uniform(0.2, 2.0, size=37)
+    p = _p(0.15, 0.3, (-7.0, -5.0, 14.0, 10.0, 140, 100), (-3.0, -4.0, 6.0, 8.0, 48, 64))
+    q = _p(0.15, -0.3, (-5.0, -7.0, 10.0, 14.0, 100, 140), (-4.0, -3.0, 8.0, 6.0, 64, 48))
+    m1, s1 = orc.make_map(p, lens, masses)
+    m2, s2 = orc.make_map(q, lens[:, ::-1].copy(), masses)
+    assert np.array_equal(m1, m2.T), "gamma-sign transpose mismatch"
+    assert s1["rays_out"] == s2["rays_out"]
+
+
+# ---------------------------------------------------------------------------
+# Pin 5: power-of-two similarity. Doubling every length and quadrupling every
+# mass scales every FP64 operation exactly by a power of two, and the
+# deflection m (x - x_k)/|x - x_k|^2 doubles with the lengths, so the map is
+# bit-identical.
+# ---------------------------------------------------------------------------
+def pin_similarity(orc, seed=12):
+    rng = np.random.default_rng(seed)
+    lens = rng.uniform(-12, 12, size=(53, 2))
+    masses = np.ones(53)
+    p = w.make_params(0.3, 0.05, 0.2, (-8.0, -6.0, 16.0, 12.0, 200, 150), (-5.0, -5.0, 10.0, 10.0, 64, 64))
+    m1, s1 = orc.make_map(p, lens, masses)
+    for k in (2.0, 0.5):
+        q = dict(p)
+        for key in ("sx0", "sy0", "sw", "sh", "tx0", "ty0", "tw", "th"):
+            q[key] = p[key] * k
+        m2, s2 = orc.make_map(q, lens * k, masses * k * k)
+        assert np.array_equal(m1, m2), f"similarity x{k} changed the map"
+        assert s1["rays_out"] == s2["rays_out"]
+    assert m1.sum() > 0
+
+
+# ---------------------------------------------------------------------------
+# Pin 6: ray conservation (every ray is binned, out, or singular).
+# ---------------------------------------------------------------------------
+def pin_conservation(orc, seed=13):
+    rng = np.random.default_rng(seed)
+    lens = rng.uniform(-6, 6, size=(29, 2))
+    p = w.make_params(0.4, 0.1, 0.2, (-5.0, -5.0, 10.0, 10.0, 123, 77), (-4.0, -4.0, 8.0, 8.0, 33, 29),
+                      window=(5, 111, 3, 70))
+    m, st = orc.make_map(p, lens)
+    assert int(m.sum()) + st["rays_out"] + st["rays_singular"] == (111 - 5) * (70 - 3)
+
+
+# ---------------------------------------------------------------------------
+# Pin 7: brute force in exact rationals on tiny grids, dyadic lens positions.
+# ---------------------------------------------------------------------------
+def pin_brute_force(orc, seeds=(0, 1, 2, 3)):
+    for seed in seeds:
+        rng = np.random.default_rng(100 + seed)
+        n_l = int(rng.integers(1, 6))
+        lens = rng.integers(-40, 40, size=(n_l, 2)) / 8.0 + 1.0 / 64
+        masses = None if seed % 2 == 0 else rng.integers(1, 16, size=n_l) / 4.0
+        sc = int(rng.integers(0, 4)) / 8.0
+        g = int(rng.integers(-4, 5)) / 8.0
+        p = _p(sc, g, (-4.0, -3.0, 8.0, 6.0, 16, 16), (-3.0, -2.5, 6.0, 5.0, 12, 10))
+        m, st = orc.make_map(p, lens, masses)
+        counts, out, sing, min_edge = exact_ref.exact_map(p, [tuple(r) for r in lens],
+                                                         None if masses is None else list(masses))
+        expect = np.zeros_like(m, dtype=np.int64)
+        for key, c in counts.items():
+            expect.flat[key] = c
+        if min_edge is not None and min_edge > F(1, 10 ** 9):
+            assert np.array_equal(m.astype(np.int64), expect), f"brute force mismatch seed {seed}"
+            assert st["rays_out"] == out and st["rays_singular"] == sing
+        else:
+            diff = int(np.abs(m.astype(np.int64) - expect).sum())
+            assert diff <= 2 * max(st["near_edge"], 1), f"brute force (near-edge case) seed {seed}"
+
+
+def pin_singular(orc):
+    """A lens exactly on a grid point: that ray is dropped and counted (Eq. (sigma) is singular there)."""
+    # grid points at (i + 1/2) * 0.25 - 2: lens at x = (5 + 1/2) * 0.25 - 2 = -0.625
+    p = _p(0.0, 0.0, (-2.0, -2.0, 4.0, 4.0, 16, 16), (-2.0, -2.0, 4.0, 4.0, 8, 8))
+    lens = np.array([[-0.625, -0.625], [1.3, 0.7]])
+    m, st = orc.make_map(p, lens)
+    counts, out, sing, _ = exact_ref.exact_map(p, [tuple(r) for r in lens])
+    assert sing == 1 and st["rays_singular"] == 1
+    pix, _, _ = orc.ray_pixels(p, lens)
+    assert pix[5 * 16 + 5] == -2
+
+
+ALL_PINS = {
+    "identity": pin_identity,
+    "separable": pin_separable,
+    "mean_mu": pin_mean_mu,
+    "point_lens": pin_point_lens,
+    "gamma_transpose": pin_gamma_transpose,
+    "similarity": pin_similarity,
+    "conservation": pin_conservation,
+    "brute_force": pin_brute_force,
+    "singular": pin_singular,
+}

@@ -1,0 +1,56 @@
+"""Pin sensitivity: plausible mistakes planted in copies of the oracle must fail a pin.
+
+Each mutant is a one-line textual change to a temporary copy of oracle.c,
+compiled on the CPU into a temporary library. The committed oracle is never
+modified. The unmutated source must pass every pin (test_oracle_pins.py).
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins
+
+MUTANTS = {
+    "sigma_c_sign": ("const double c1 = (1.0 - p->gamma) - p->sigma_c;",
+                     "const double c1 = (1.0 - p->gamma) + p->sigma_c;"),
+    "shear_axis_swapped": ("const double c1 = (1.0 - p->gamma) - p->sigma_c;",
+                           "const double c1 = (1.0 + p->gamma) - p->sigma_c;"),
+    "deflection_power": ("const double f = m / r2;", "const double f = m / sqrt(r2);"),
+    "deflection_sign": ("a1 += f * d1;", "a1 -= f * d1;"),
+    "dropped_y_term_in_r2": ("const double r2 = d1 * d1 + d2 * d2;", "const double r2 = d1 * d1 + d1 * d1;"),
+    "wrong_lens_index": ("const double d2 = x2 - lens_xy[2 * k + 1];", "const double d2 = x2 - lens_xy[2 * k];"),
+    "mass_ignored": ("const double m = lens_m ? lens_m[k] : 1.0;", "const double m = 1.0;"),
+    "corner_rays": ("const double x1 = p->sx0 + ((double)i + 0.5) * (p->sw / (double)p->nx);",
+                    "const double x1 = p->sx0 + ((double)i) * (p->sw / (double)p->nx);"),
+    "spacing_uses_ny": ("(p->sw / (double)p->nx)", "(p->sw / (double)p->ny)"),
+    "pixel_size_uses_npx": ("r.v = (y2 - p->ty0) / (p->th / (double)p->npy);",
+                            "r.v = (y2 - p->ty0) / (p->th / (double)p->npx);"),
+    "closed_low_edge": ("r.u >= 0.0 && r.u < (double)p->npx", "r.u > 0.0 && r.u < (double)p->npx"),
+    "closed_high_edge": ("r.v >= 0.0 && r.v < (double)p->npy", "r.v >= 0.0 && r.v <= (double)p->npy"),
+    "map_transposed": ("r.pix = (int64_t)floor(r.v) * p->npx + (int64_t)floor(r.u);",
+                       "r.pix = (int64_t)floor(r.u) * p->npy + (int64_t)floor(r.v);"),
+    "singular_counted_as_out": ("r.pix = RAY_SINGULAR;\n            return r;",
+                                "r.pix = RAY_OUT;\n            return r;"),
+    "macro_term_dropped": ("const double y2 = c2 * x2 - a2;", "const double y2 = x2 - a2;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found for {name}"
+    mutated = src.replace(old, new, 1)
+    path = tmp_path / "oracle_mut.c"
+    path.write_text(mutated)
+    lib = oracle.build(force=True, src=str(path), out=str(tmp_path / f"liboracle_{name}.so"),
+                       extra_flags=("-w",))
+    orc = oracle.load(lib)
+    failed = []
+    for pin_name, pin in oracle_pins.ALL_PINS.items():
+        try:
+            pin(orc)
+        except (AssertionError, RuntimeError):
+            failed.append(pin_name)
+    assert failed, f"no pin caught mutant {name}"
