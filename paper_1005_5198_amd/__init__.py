@@ -1,0 +1,21 @@
+"""MI355X-native inverse ray-shooting for gravitational-microlensing magnification maps.
+
+Public entry points (loaded lazily so that importing the package, e.g. for
+``paper_1005_5198_amd.workloads``, does not need the HIP library):
+
+    make_map(params, lens_xy, lens_m=None, mode="mixed") -> torch.uint32 [npy, npx]
+    ray_pixels(params, lens_xy, lens_m=None, mode="mixed") -> torch.int32 [rays in window]
+    read_stats(workspace) -> dict
+
+``params`` is a dict with the fields of ``rs_map_params`` (see include/rayshoot.h);
+``paper_1005_5198_amd.workloads.make_params`` builds one.
+"""
+_API = ("make_map", "ray_pixels", "read_stats", "workspace_bytes", "new_workspace", "to_params",
+        "lens_tensors", "profile_enable", "profile_read", "version")
+
+
+def __getattr__(name):
+    if name in _API:
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

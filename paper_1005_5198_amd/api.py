@@ -1,0 +1,137 @@
+"""Python entry points over the C ABI: make_map, ray_pixels, read_stats.
+
+PyTorch supplies device memory and the stream; every step of the computation
+runs in the library's HIP kernels. Inputs given as numpy arrays are copied to
+the device first.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+MODES = {"fp32": L.RS_FP32, "mixed": L.RS_MIXED}
+
+
+def to_params(p: dict, mode: str = "mixed", accumulate: bool = False) -> L.MapParams:
+    """Build the C parameter struct from a workloads-style dict (keys of MapParams)."""
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
+    s = L.MapParams()
+    for name, _ in L.MapParams._fields_:
+        if name == "mode":
+            s.mode = MODES[mode]
+        elif name == "flags":
+            s.flags = L.RS_ACCUMULATE if accumulate else 0
+        else:
+            setattr(s, name, p[name])
+    return s
+
+
+def _device():
+    if not torch.cuda.is_available():
+        raise RuntimeError("a HIP device is required (torch.cuda.is_available() is False)")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def lens_tensors(lens_xy, lens_m=None, device=None):
+    """float64 device tensors [N,2] and [N] (or None) from numpy arrays or tensors."""
+    device = device or _device()
+    xy = torch.as_tensor(lens_xy, dtype=torch.float64).reshape(-1, 2).to(device).contiguous()
+    m = None
+    if lens_m is not None:
+        m = torch.as_tensor(lens_m, dtype=torch.float64).reshape(-1).to(device).contiguous()
+        if m.shape[0] != xy.shape[0]:
+            raise ValueError("lens_m and lens_xy differ in length")
+    return xy, m
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None or t.numel() == 0 else t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def workspace_bytes(params: dict, n_lens: int, mode: str = "mixed") -> int:
+    c = to_params(params, mode)
+    n = L.lib().rs_workspace_bytes(ctypes.byref(c), int(n_lens))
+    if n == 0:
+        L.check(L.RS_EINVAL)
+    return int(n)
+
+
+def new_workspace(params: dict, n_lens: int, mode: str = "mixed", device=None) -> torch.Tensor:
+    return torch.empty(workspace_bytes(params, n_lens, mode), dtype=torch.uint8, device=device or _device())
+
+
+def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optional[torch.Tensor] = None,
+             workspace: Optional[torch.Tensor] = None, accumulate: bool = False, stream=None,
+             return_stats: bool = False):
+    """Count map uint32 [npy, npx] of the params' ray window (Section 2, Eq. (sigma), Eq. (mu_ij)).
+
+    Asynchronous on the stream unless return_stats is set (then it synchronises
+    and also returns the counters as a dict).
+    """
+    dev = _device()
+    xy, m = lens_tensors(lens_xy, lens_m, dev)
+    c = to_params(params, mode, accumulate)
+    if out is None:
+        out = torch.empty((int(params["npy"]), int(params["npx"])), dtype=torch.uint32, device=dev)
+    if out.dtype != torch.uint32 or not out.is_contiguous() or tuple(out.shape) != (c.npy, c.npx):
+        raise ValueError("out must be a contiguous uint32 tensor of shape (npy, npx)")
+    if workspace is None:
+        workspace = new_workspace(params, xy.shape[0], mode, dev)
+    h = _stream_handle(stream)
+    L.check(L.lib().rs_make_map(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], out.data_ptr(),
+                                workspace.data_ptr(), workspace.numel(), h))
+    if return_stats:
+        return out, read_stats(workspace, stream)
+    return out
+
+
+def ray_pixels(params: dict, lens_xy, lens_m=None, mode: str = "mixed", workspace=None, stream=None,
+               return_stats: bool = False):
+    """Per-ray pixel index int32 over the window (row-major): v*npx+u, -1 out, -2 singular."""
+    dev = _device()
+    xy, m = lens_tensors(lens_xy, lens_m, dev)
+    c = to_params(params, mode)
+    n = int((params["i1"] - params["i0"]) * (params["j1"] - params["j0"]))
+    pix = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = new_workspace(params, xy.shape[0], mode, dev)
+    L.check(L.lib().rs_ray_pixels(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], pix.data_ptr(),
+                                  workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+    pix = pix[:n]
+    if return_stats:
+        return pix, read_stats(workspace, stream)
+    return pix
+
+
+def read_stats(workspace: torch.Tensor, stream=None) -> dict:
+    st = L.MapStats()
+    L.check(L.lib().rs_read_stats(workspace.data_ptr(), ctypes.byref(st), _stream_handle(stream)))
+    return st.as_dict()
+
+
+def profile_enable(on: bool = True) -> None:
+    L.check(L.lib().rs_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(kernel milliseconds, launches, interactions) of the deflection launches since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    inter = ctypes.c_double()
+    L.check(L.lib().rs_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(inter)))
+    return ms.value, n.value, inter.value
+
+
+def version() -> str:
+    return L.lib().rs_version().decode()

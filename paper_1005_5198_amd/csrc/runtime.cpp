@@ -1,0 +1,271 @@
+// Host runtime of the C ABI declared in include/rayshoot.h: argument
+// validation, planning of ray chunks and workspace, and the launch sequence
+// (zero map and counters -> per chunk: deflection kernel, FP64 re-check).
+#include "rs_internal.h"
+#include "rayshoot.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace rs {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(RS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Plan {
+    int64_t W = 0, H = 0;
+    int64_t rows_per_chunk = 0, n_chunks = 0;
+    int64_t queue_cap = 0;   // uint32 entries (mixed only)
+    size_t qcount_bytes = 0; // WS_QCOUNT + 4 * n_chunks, 256-aligned
+    size_t bytes = 0;
+};
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const rs_map_params *p, int64_t n_lens) {
+    if (!p) return fail(RS_EINVAL, "params is NULL");
+    if (p->nx <= 0 || p->ny <= 0) return fail(RS_EINVAL, "ray grid must be positive (nx=%lld ny=%lld)", (long long)p->nx, (long long)p->ny);
+    if (p->npx <= 0 || p->npy <= 0) return fail(RS_EINVAL, "source grid must be positive");
+    if (p->npx * p->npy >= (int64_t(1) << 31)) return fail(RS_EINVAL, "source map must have fewer than 2^31 pixels");
+    if (!finite_pos(p->sw) || !finite_pos(p->sh)) return fail(RS_EINVAL, "shooting extents must be finite and > 0");
+    if (!finite_pos(p->tw) || !finite_pos(p->th)) return fail(RS_EINVAL, "source extents must be finite and > 0");
+    if (!std::isfinite(p->sx0) || !std::isfinite(p->sy0) || !std::isfinite(p->tx0) || !std::isfinite(p->ty0))
+        return fail(RS_EINVAL, "grid origins must be finite");
+    if (!std::isfinite(p->gamma) || !std::isfinite(p->sigma_c) || !std::isfinite(p->sigma_star))
+        return fail(RS_EINVAL, "gamma, sigma_c and sigma_star must be finite");
+    if (p->i0 < 0 || p->i1 > p->nx || p->i0 > p->i1 || p->j0 < 0 || p->j1 > p->ny || p->j0 > p->j1)
+        return fail(RS_EINVAL, "ray window [%lld,%lld)x[%lld,%lld) outside the %lldx%lld grid", (long long)p->i0,
+                    (long long)p->i1, (long long)p->j0, (long long)p->j1, (long long)p->nx, (long long)p->ny);
+    if (p->nx >= (int64_t(1) << 52) || p->ny >= (int64_t(1) << 52)) return fail(RS_EINVAL, "ray grid too large");
+    if (p->i1 - p->i0 > (int64_t(1) << 26)) return fail(RS_EINVAL, "window wider than 2^26 rays");
+    if (p->mode != RS_FP32 && p->mode != RS_MIXED) return fail(RS_EINVAL, "mode must be RS_FP32 or RS_MIXED");
+    if (p->flags & ~RS_ACCUMULATE) return fail(RS_EINVAL, "unknown flags 0x%x", p->flags);
+    if (n_lens < 0) return fail(RS_EINVAL, "n_lens < 0");
+    return RS_OK;
+}
+
+Plan make_plan(const rs_map_params *p) {
+    Plan pl;
+    pl.W = p->i1 - p->i0;
+    pl.H = p->j1 - p->j0;
+    int64_t rows = pl.W > 0 ? CHUNK_RAYS / pl.W : PATCH_Y;
+    rows = rows / PATCH_Y * PATCH_Y;
+    if (rows < PATCH_Y) rows = PATCH_Y;
+    pl.rows_per_chunk = rows;
+    pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
+    const int64_t rows_cap = pl.H < rows ? pl.H : rows;
+    pl.queue_cap = (p->mode == RS_MIXED) ? rows_cap * pl.W : 0;
+    pl.qcount_bytes = (WS_QCOUNT + 4 * (size_t)pl.n_chunks + 255) / 256 * 256;
+    pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
+    return pl;
+}
+
+struct Profile {
+    std::mutex mu;
+    bool on = false;
+    struct Rec { hipEvent_t a, b; double inter; };
+    std::vector<Rec> pending;
+    double ms = 0.0, inter = 0.0;
+    int64_t launches = 0;
+};
+static Profile g_prof;
+
+// Enqueue the whole map (or pixel) computation. map may be null when pix is set.
+int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                uint32_t *map, int32_t *pix, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    int rc = validate(p, n_lens);
+    if (rc) return rc;
+    if (n_lens > 0 && !lens_xy) return fail(RS_EINVAL, "lens_xy is NULL");
+    if (!map && !pix) return fail(RS_EINVAL, "output is NULL");
+    if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(lens_xy) | reinterpret_cast<uintptr_t>(lens_m)) & 7)
+        return fail(RS_EINVAL, "lens arrays must be 8-byte aligned");
+    const Plan pl = make_plan(p);
+    if (workspace_bytes < pl.bytes)
+        return fail(RS_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, pl.bytes);
+
+    const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
+    hipError_t e = launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, pl.n_chunks, stream);
+    if (e != hipSuccess) return hip_fail(e, "fill kernel");
+
+    char *ws = static_cast<char *>(workspace);
+    ShootArgs a{};
+    a.sx0 = p->sx0;
+    a.sy0 = p->sy0;
+    a.spx = p->sw / (double)p->nx;
+    a.spy = p->sh / (double)p->ny;
+    a.i0 = p->i0;
+    a.i1 = p->i1;
+    a.j0 = p->j0;
+    a.nbx = (pl.W + PATCH_X - 1) / PATCH_X;
+    a.c1 = (1.0 - p->gamma) - p->sigma_c;
+    a.c2 = (1.0 + p->gamma) - p->sigma_c;
+    a.tx0 = p->tx0;
+    a.ty0 = p->ty0;
+    a.inv_pixw = (double)p->npx / p->tw;
+    a.inv_pixh = (double)p->npy / p->th;
+    a.npx = p->npx;
+    a.npy = p->npy;
+    a.lens_xy = lens_xy;
+    a.lens_m = lens_m;
+    a.n_lens = n_lens;
+    a.bound_scale = 1.0 + (double)(n_lens + 64) * 4.7e-10;
+    a.map = map;
+    a.pix_out = pix;
+    a.counters = reinterpret_cast<unsigned long long *>(ws + WS_COUNTERS);
+    a.queue = reinterpret_cast<uint32_t *>(ws + pl.qcount_bytes);
+
+    RecheckArgs r{};
+    r.sx0 = p->sx0;
+    r.sy0 = p->sy0;
+    r.sw = p->sw;
+    r.sh = p->sh;
+    r.nx = p->nx;
+    r.ny = p->ny;
+    r.i0 = p->i0;
+    r.i1 = p->i1;
+    r.j0 = p->j0;
+    r.gamma = p->gamma;
+    r.sigma_c = p->sigma_c;
+    r.tx0 = p->tx0;
+    r.ty0 = p->ty0;
+    r.tw = p->tw;
+    r.th = p->th;
+    r.npx = p->npx;
+    r.npy = p->npy;
+    r.lens_xy = lens_xy;
+    r.lens_m = lens_m;
+    r.n_lens = n_lens;
+    r.map = map;
+    r.pix_out = pix;
+    r.counters = a.counters;
+    r.queue = a.queue;
+
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        prof = g_prof.on;
+    }
+    for (int64_t c = 0; c < pl.n_chunks; ++c) {
+        a.jc0 = p->j0 + c * pl.rows_per_chunk;
+        a.jc1 = a.jc0 + pl.rows_per_chunk < p->j1 ? a.jc0 + pl.rows_per_chunk : p->j1;
+        a.qcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + c;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (prof) {
+            if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+                return fail(RS_EHIP, "hipEventCreate failed");
+            if (hipEventRecord(ev0, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
+        }
+        e = launch_shoot(a, p->mode, stream);
+        if (e != hipSuccess) return hip_fail(e, "deflection kernel");
+        if (prof) {
+            if (hipEventRecord(ev1, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
+            std::lock_guard<std::mutex> lk(g_prof.mu);
+            g_prof.pending.push_back({ev0, ev1, (double)(a.jc1 - a.jc0) * (double)pl.W * (double)n_lens});
+        }
+        if (p->mode == RS_MIXED) {
+            r.jc0 = a.jc0;
+            r.qcount = a.qcount;
+            e = launch_recheck(r, (a.jc1 - a.jc0) * pl.W, stream);
+            if (e != hipSuccess) return hip_fail(e, "re-check kernel");
+        }
+    }
+    return RS_OK;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+const char *rs_version(void) { return "rayshoot-mi355x 0.1 (gfx950)"; }
+
+const char *rs_last_error(void) { return g_last_error.c_str(); }
+
+size_t rs_workspace_bytes(const rs_map_params *params, int64_t n_lens) {
+    if (validate(params, n_lens) != RS_OK) return 0;
+    return make_plan(params).bytes;
+}
+
+int rs_make_map(const rs_map_params *params, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                uint32_t *map, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!map) return fail(RS_EINVAL, "map is NULL");
+    return enqueue_map(params, lens_xy, lens_m, n_lens, map, nullptr, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
+}
+
+int rs_ray_pixels(const rs_map_params *params, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                  int32_t *pix, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!pix) return fail(RS_EINVAL, "pix is NULL");
+    return enqueue_map(params, lens_xy, lens_m, n_lens, nullptr, pix, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
+}
+
+int rs_read_stats(const void *workspace, rs_map_stats *stats_host, void *stream) {
+    if (!workspace || !stats_host) return fail(RS_EINVAL, "NULL argument");
+    unsigned long long c[8];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(c, static_cast<const char *>(workspace) + WS_COUNTERS, sizeof(c),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading stats");
+    stats_host->rays_in_map = c[C_IN];
+    stats_host->rays_out = c[C_OUT];
+    stats_host->rays_singular = c[C_SING];
+    stats_host->rays_rechecked = c[C_RECHECK];
+    stats_host->rays_shot = c[C_IN] + c[C_OUT] + c[C_SING];
+    return RS_OK;
+}
+
+int rs_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return RS_OK;
+}
+
+int rs_profile_read(double *kernel_ms, int64_t *launches, double *interactions) {
+    std::vector<Profile::Rec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        recs.swap(g_prof.pending);
+    }
+    double ms_sum = 0.0, inter = 0.0;
+    int64_t n = 0;
+    int rc = RS_OK;
+    for (auto &r : recs) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) rc = hip_fail(e, "reading kernel timing");
+        ms_sum += ms;
+        inter += r.inter;
+        ++n;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    if (kernel_ms) *kernel_ms = ms_sum;
+    if (launches) *launches = n;
+    if (interactions) *interactions = inter;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,386 @@
+// Deflection + binning kernel for inverse ray-shooting on gfx950.
+//
+// Computes, for every ray of a chunk of the ray window, the lens equation of
+// Section 2, Eq. (sigma),
+//     y = diag(1 - gamma - sigma_c, 1 + gamma - sigma_c) x - sum_k m_k (x - x_k)/|x - x_k|^2,
+// and bins it into the source-plane count map of Eq. (mu_ij).
+//
+// Design (gfx950, FP32 VALU bound; no MFMA since the sum is not a contraction):
+//  * A block owns a 64 x 32 patch of rays. Lenses stream through LDS in tiles
+//    of LENS_TILE, converted once per block from FP64 to FP32 offsets relative
+//    to the patch centre, so FP32 carries small numbers and the per-block
+//    conversion is paid once per lens per 2048 rays.
+//  * Each lane owns 4 x 2 rays; per lens it computes dx for 4 columns and dy,
+//    dy^2 for 2 rows, then r^2 = fma(dx, dx, dy^2), v_rcp_f32, and two FMAs
+//    per ray. Every LDS read is a 16-byte broadcast of two lenses.
+//  * The sum runs in FP32 over GROUP lenses, then each partial is folded
+//    exactly into an FP64 accumulator, so FP32 rounding never sees the large
+//    running total.
+//  * Mixed mode: while staging lenses the block also sums a rigorous bound on
+//    the FP32 error of every ray in the patch (lenses close to the patch are
+//    bounded per ray instead). A ray whose bound reaches a pixel edge goes to a
+//    queue that an FP64 kernel re-evaluates with the plain definition.
+//  * Binning uses wave-aggregated atomics: lanes that hit the same pixel add
+//    their count with one atomic.
+#include "rs_internal.h"
+
+namespace rs {
+namespace {
+
+constexpr double U32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
+
+// Per-lens FP32 error constants (derivation in the design notes):
+//   |t_hat - t| <= u m (K_TERM |dx| + K_H h) / r^2 for one term t = m dx / r^2,
+//   the FP32 group sum adds u (GROUP - pos) |t_hat| for the lens at position pos.
+// Unit masses: K_TERM covers dx (2.04u), r^2 (6.08u + 4.08u h/r) and rcp (2u, 1 ulp);
+// with masses, the FP32 mass rounding and the extra multiply add 2u more.
+constexpr double K_TERM_UNIT = 10.5;
+constexpr double K_TERM_MASS = 13.0;
+constexpr double K_GROUP = 1.01;
+constexpr double K_H = 6.5;
+
+constexpr int OUT = -1;
+constexpr int SINGULAR = -2;
+constexpr int FLAGGED = -3;
+
+struct NearLens {
+    float x, y, m;
+    int pos;
+};
+
+__device__ __forceinline__ double ray_coord(double origin, int64_t idx, double spacing) {
+    // The definition's own operations: origin + ((double)idx + 0.5) * spacing.
+    // The library is built without floating-point contraction.
+    return origin + ((double)idx + 0.5) * spacing;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Add one count per lane to map[p] for every lane with p >= 0, one atomic per distinct pixel.
+__device__ __forceinline__ void aggregated_add(uint32_t *map, int p) {
+    uint64_t pending = __ballot(p >= 0);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int lp = __builtin_amdgcn_readlane(p, leader);
+        const uint64_t same = __ballot(p == lp) & pending;
+        if (lane_id() == leader) atomicAdd(map + lp, (uint32_t)__builtin_popcountll(same));
+        pending &= ~same;
+    }
+}
+
+template <bool UNIT, int MODE, bool PIX>
+__global__ __launch_bounds__(BLOCK_THREADS) void shoot_kernel(const ShootArgs a) {
+    __shared__ float4 tile[LENS_TILE];        // UNIT: two (x,y) pairs per float4; else (x,y,m,0)
+    __shared__ NearLens near_list[NEAR_MAX];
+    __shared__ int near_count;
+    __shared__ double red_bx[BLOCK_THREADS / 64], red_by[BLOCK_THREADS / 64];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wx = wave % WAVES_X, wy = wave / WAVES_X;
+    const int lx = lane % LANES_X, ly = lane / LANES_X;
+
+    // Patch of this block.
+    const int64_t pbx = blockIdx.x % a.nbx;
+    const int64_t pby = blockIdx.x / a.nbx;
+    const int64_t ib = a.i0 + pbx * PATCH_X;
+    const int64_t jb = a.jc0 + pby * PATCH_Y;
+    // Patch origin and half-extents (with a spacing of slack on each side).
+    const double ox = a.sx0 + ((double)ib + 0.5 * PATCH_X) * a.spx;
+    const double oy = a.sy0 + ((double)jb + 0.5 * PATCH_Y) * a.spy;
+    const double hx = (0.5 * PATCH_X + 1.0) * a.spx;
+    const double hy = (0.5 * PATCH_Y + 1.0) * a.spy;
+    const double h = sqrt(hx * hx + hy * hy);
+    const double near_r2 = 4.0 * h * h;
+
+    // This lane's rays: FP32 offsets from the patch origin.
+    float rxl[RX], ryl[RY];
+    int64_t ri[RX], rj[RY];
+#pragma unroll
+    for (int c = 0; c < RX; ++c) {
+        ri[c] = ib + c * STRIDE_X + wx * LANES_X + lx;
+        rxl[c] = (float)(ray_coord(a.sx0, ri[c], a.spx) - ox);
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        rj[r] = jb + r * STRIDE_Y + wy * LANES_Y + ly;
+        ryl[r] = (float)(ray_coord(a.sy0, rj[r], a.spy) - oy);
+    }
+
+    double Ax[RY][RX], Ay[RY][RX];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) {
+            Ax[r][c] = 0.0;
+            Ay[r][c] = 0.0;
+        }
+
+    if (tid == 0) near_count = 0;
+    double bx = 0.0, by = 0.0;  // this thread's share of the block error bound (units of u)
+    const double k_term = UNIT ? K_TERM_UNIT : K_TERM_MASS;
+
+    for (int64_t t0 = 0; t0 < a.n_lens; t0 += LENS_TILE) {
+        const int cnt = (int)((a.n_lens - t0) < LENS_TILE ? (a.n_lens - t0) : LENS_TILE);
+        const int cnt_pad = (cnt + GROUP - 1) / GROUP * GROUP;
+        __syncthreads();  // previous tile fully consumed (and near_count initialised)
+        for (int s = tid; s < cnt_pad; s += BLOCK_THREADS) {
+            float fx = 1.0e18f, fy = 0.0f, fm = 0.0f;  // padding lens: far away, massless
+            if (s < cnt) {
+                const int64_t k = t0 + s;
+                const double X = a.lens_xy[2 * k];
+                const double Y = a.lens_xy[2 * k + 1];
+                const double m = UNIT ? 1.0 : a.lens_m[k];
+                const double Lx = X - ox, Ly = Y - oy;
+                fx = (float)Lx;
+                fy = (float)Ly;
+                fm = (float)m;
+                if (MODE == 1) {
+                    const double alx = fabs(Lx), aly = fabs(Ly);
+                    const double ex = fmax(alx - hx, 0.0), ey = fmax(aly - hy, 0.0);
+                    const double dmin2 = ex * ex + ey * ey;
+                    const int pos = s % GROUP;
+                    if (dmin2 < near_r2) {
+                        const int q = atomicAdd(&near_count, 1);
+                        if (q < NEAR_MAX) near_list[q] = NearLens{fx, fy, (float)fabs(m), pos};
+                    } else {
+                        const double wgt = k_term + K_GROUP * (double)(GROUP - pos);
+                        const double im = fabs(m) / dmin2;
+                        bx += im * (wgt * (alx + hx) + K_H * h);
+                        by += im * (wgt * (aly + hy) + K_H * h);
+                    }
+                }
+            }
+            if (UNIT) {
+                float *t2 = reinterpret_cast<float *>(tile);
+                t2[2 * s] = fx;
+                t2[2 * s + 1] = fy;
+            } else {
+                tile[s] = make_float4(fx, fy, fm, 0.0f);
+            }
+        }
+        __syncthreads();
+
+        for (int g = 0; g < cnt_pad; g += GROUP) {
+            float sx[RY][RX], sy[RY][RX];
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int c = 0; c < RX; ++c) {
+                    sx[r][c] = 0.0f;
+                    sy[r][c] = 0.0f;
+                }
+            if (UNIT) {
+#pragma unroll
+                for (int kk = 0; kk < GROUP; kk += 2) {
+                    const float4 q = tile[(g + kk) >> 1];
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const float LX = half ? q.z : q.x;
+                        const float LY = half ? q.w : q.y;
+                        float dy[RY], dy2[RY], dx[RX];
+#pragma unroll
+                        for (int r = 0; r < RY; ++r) {
+                            dy[r] = ryl[r] - LY;
+                            dy2[r] = dy[r] * dy[r];
+                        }
+#pragma unroll
+                        for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - LX;
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+#pragma unroll
+                            for (int c = 0; c < RX; ++c) {
+                                const float r2 = __builtin_fmaf(dx[c], dx[c], dy2[r]);
+                                const float inv = __builtin_amdgcn_rcpf(r2);
+                                sx[r][c] = __builtin_fmaf(dx[c], inv, sx[r][c]);
+                                sy[r][c] = __builtin_fmaf(dy[r], inv, sy[r][c]);
+                            }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < GROUP; ++kk) {
+                    const float4 q = tile[g + kk];
+                    float dy[RY], dy2[RY], dx[RX];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r) {
+                        dy[r] = ryl[r] - q.y;
+                        dy2[r] = dy[r] * dy[r];
+                    }
+#pragma unroll
+                    for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - q.x;
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+#pragma unroll
+                        for (int c = 0; c < RX; ++c) {
+                            const float r2 = __builtin_fmaf(dx[c], dx[c], dy2[r]);
+                            const float inv = q.z * __builtin_amdgcn_rcpf(r2);
+                            sx[r][c] = __builtin_fmaf(dx[c], inv, sx[r][c]);
+                            sy[r][c] = __builtin_fmaf(dy[r], inv, sy[r][c]);
+                        }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int c = 0; c < RX; ++c) {
+                    Ax[r][c] += (double)sx[r][c];
+                    Ay[r][c] += (double)sy[r][c];
+                }
+        }
+    }
+
+    // Block-wide error bound (mixed mode).
+    double Bx = 0.0, By = 0.0;
+    int n_near = 0;
+    bool all_flagged = false;
+    if (MODE == 1) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            bx += __shfl_xor(bx, off);
+            by += __shfl_xor(by, off);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            red_bx[wave] = bx;
+            red_by[wave] = by;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < BLOCK_THREADS / 64; ++w) {
+            Bx += red_bx[w];
+            By += red_by[w];
+        }
+        n_near = near_count;
+        all_flagged = n_near > NEAR_MAX;
+        if (all_flagged) n_near = 0;
+    }
+
+    // Epilogue: macro terms, pixel, classification, binning.
+    const float h_f = (float)h;
+    const float tiny_r2 = 1.0e-6f * h_f * h_f;
+    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
+    const int64_t W = a.i1 - a.i0;
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) {
+            const int64_t i = ri[c], j = rj[r];
+            const bool valid = (i < a.i1) && (j < a.jc1);
+            const double x1 = ray_coord(a.sx0, i, a.spx);
+            const double x2 = ray_coord(a.sy0, j, a.spy);
+            const double y1 = a.c1 * x1 - Ax[r][c];
+            const double y2 = a.c2 * x2 - Ay[r][c];
+            const double u = (y1 - a.tx0) * a.inv_pixw;
+            const double v = (y2 - a.ty0) * a.inv_pixh;
+            int code;
+            if (MODE == 0) {
+                if (!(isfinite(u) && isfinite(v))) code = SINGULAR;
+                else if (u >= 0.0 && u < (double)a.npx && v >= 0.0 && v < (double)a.npy)
+                    code = (int)((int64_t)floor(v) * a.npx + (int64_t)floor(u));
+                else code = OUT;
+            } else {
+                // Per-ray bound from the lenses next to the patch.
+                float cx = 0.0f, cy = 0.0f;
+                for (int q = 0; q < n_near; ++q) {
+                    const NearLens nl = near_list[q];
+                    const float dxn = rxl[c] - nl.x, dyn = ryl[r] - nl.y;
+                    const float r2n = dxn * dxn + dyn * dyn;
+                    const float wgt = (float)(k_term + K_GROUP * (double)(GROUP - nl.pos));
+                    if (!(r2n > tiny_r2)) {
+                        cx = __builtin_inff();
+                        cy = __builtin_inff();
+                    } else {
+                        const float im = nl.m / (0.999f * r2n);
+                        cx += im * (wgt * (1.001f * fabsf(dxn) + 1e-6f * h_f) + (float)K_H * h_f);
+                        cy += im * (wgt * (1.001f * fabsf(dyn) + 1e-6f * h_f) + (float)K_H * h_f);
+                    }
+                }
+                const double ea = 1e-15 + 8.9e-16 * (fabs(a.c1 * x1) + fabs(Ax[r][c]) + fabs(a.tx0));
+                const double eb = 1e-15 + 8.9e-16 * (fabs(a.c2 * x2) + fabs(Ay[r][c]) + fabs(a.ty0));
+                const double Eu = (U32 * (Bx + (double)cx) * a.bound_scale + ea) * a.inv_pixw * 1.000001;
+                const double Ev = (U32 * (By + (double)cy) * a.bound_scale + eb) * a.inv_pixh * 1.000001;
+                const double fu = floor(u), fv = floor(v);
+                const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Eu) && (fu >= 0.0) && (fu < (double)a.npx);
+                const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Ev) && (fv >= 0.0) && (fv < (double)a.npy);
+                const bool out_u = (u < -Eu) || (u > (double)a.npx + Eu);
+                const bool out_v = (v < -Ev) || (v > (double)a.npy + Ev);
+                if (all_flagged) code = FLAGGED;
+                else if (ok_u && ok_v) code = (int)((int64_t)fv * a.npx + (int64_t)fu);
+                else if (out_u || out_v) code = OUT;
+                else code = FLAGGED;
+            }
+            if (!valid) code = INT32_MIN;
+
+            n_in += __builtin_popcountll(__ballot(code >= 0));
+            n_out += __builtin_popcountll(__ballot(code == OUT));
+            n_sing += __builtin_popcountll(__ballot(code == SINGULAR));
+
+            if (PIX) {
+                if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+            } else {
+                aggregated_add(a.map, code);
+            }
+            if (MODE == 1) {
+                const uint64_t fl = __ballot(code == FLAGGED);
+                if (fl) {
+                    const int first = __builtin_ctzll(fl);
+                    uint32_t base = 0;
+                    if (lane == first) base = atomicAdd(a.qcount, (uint32_t)__builtin_popcountll(fl));
+                    base = __builtin_amdgcn_readlane(base, first);
+                    if (code == FLAGGED) {
+                        const uint32_t below = (uint32_t)__builtin_popcountll(fl & ((1ull << lane) - 1ull));
+                        a.queue[base + below] = (uint32_t)((j - a.jc0) * W + (i - a.i0));
+                    }
+                }
+            }
+        }
+    if (lane == 0) {
+        if (n_in) atomicAdd(a.counters + C_IN, n_in);
+        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
+        if (n_sing) atomicAdd(a.counters + C_SING, n_sing);
+    }
+}
+
+__global__ void fill_kernel(uint32_t *map, int64_t n_pix, uint32_t *ws_words, int64_t n_ws_words) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_pix; t += stride) map[t] = 0u;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_ws_words; t += stride)
+        ws_words[t] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_qcount,
+                       hipStream_t stream) {
+    const int64_t n_ws_words = (int64_t)(WS_QCOUNT / 4) + n_qcount;
+    const int64_t work = (map ? n_pix : 0) > n_ws_words ? (map ? n_pix : 0) : n_ws_words;
+    int blocks = (int)((work + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, stream, map, map ? n_pix : 0,
+                       static_cast<uint32_t *>(workspace), n_ws_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_shoot(const ShootArgs &a, int mode, hipStream_t stream) {
+    const int64_t nby = (a.jc1 - a.jc0 + PATCH_Y - 1) / PATCH_Y;
+    const int64_t blocks = a.nbx * nby;
+    if (blocks <= 0) return hipSuccess;
+    const bool unit = a.lens_m == nullptr;
+    const bool pix = a.pix_out != nullptr;
+    const dim3 grid((unsigned)blocks), block(BLOCK_THREADS);
+#define RS_LAUNCH(U, M, P) hipLaunchKernelGGL((shoot_kernel<U, M, P>), grid, block, 0, stream, a)
+    if (mode == 0) {
+        if (unit) { if (pix) RS_LAUNCH(true, 0, true); else RS_LAUNCH(true, 0, false); }
+        else { if (pix) RS_LAUNCH(false, 0, true); else RS_LAUNCH(false, 0, false); }
+    } else {
+        if (unit) { if (pix) RS_LAUNCH(true, 1, true); else RS_LAUNCH(true, 1, false); }
+        else { if (pix) RS_LAUNCH(false, 1, true); else RS_LAUNCH(false, 1, false); }
+    }
+#undef RS_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace rs

@@ -1,0 +1,82 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+validates arguments before touching a device. No compute calls (no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(rs_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1005_5198_amd import _lib
+    return _lib.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_only_exported_names(lib):
+    from paper_1005_5198_amd import _lib
+    assert set(_lib.exported_symbols()) <= set(declared_functions())
+
+
+def test_version(lib):
+    from paper_1005_5198_amd import api
+    assert "gfx950" in api.version()
+
+
+def test_workspace_bytes_and_validation(lib):
+    from paper_1005_5198_amd import api, workloads as w
+    s = w.config2()
+    n_mixed = api.workspace_bytes(s.params, s.n_lens, "mixed")
+    n_fp32 = api.workspace_bytes(s.params, s.n_lens, "fp32")
+    assert n_fp32 < n_mixed
+    # the mixed queue holds one launch's rays: whole 32-row bands of the window, at most 2^26 rays
+    rows = (1 << 26) // 19200 // 32 * 32
+    assert n_mixed >= 4 * rows * 19200 and n_mixed < 4 * (1 << 26) + 65536
+    bad = dict(s.params)
+    bad["i1"] = bad["nx"] + 1
+    c = api.to_params(bad)
+    assert lib.rs_workspace_bytes(ctypes.byref(c), s.n_lens) == 0
+    assert b"window" in lib.rs_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("npy", -3), ("sw", 0.0), ("th", float("nan")),
+                                         ("j0", -1), ("gamma", float("inf")), ("mode", 7)])
+def test_make_map_rejects_before_device_work(lib, field, value):
+    from paper_1005_5198_amd import api, _lib, workloads as w
+    s = w.config0()
+    p = dict(s.params)
+    c = api.to_params(p)
+    setattr(c, field, value)
+    rc = lib.rs_make_map(ctypes.byref(c), None, None, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
+    assert rc == _lib.RS_EINVAL
+    assert lib.rs_last_error()
+
+
+def test_make_map_rejects_null_outputs(lib):
+    from paper_1005_5198_amd import api, _lib, workloads as w
+    s = w.config0()
+    c = api.to_params(s.params)
+    assert lib.rs_make_map(ctypes.byref(c), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None) == _lib.RS_EINVAL
+    assert lib.rs_make_map(ctypes.byref(c), None, None, 5, ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30,
+                           None) == _lib.RS_EINVAL

@@ -1,0 +1,209 @@
+"""HIP path vs the FP64 oracle on the same seeded inputs (needs an MI355X).
+
+Tolerances (from the method's definition of the count map):
+  * RS_MIXED: every ray's pixel and the whole uint32 map equal the oracle's,
+    bit for bit. The oracle's near-edge list (rays within 1e-9 px of an edge)
+    is reported alongside.
+  * RS_FP32: at most 1e-4 of the rays may land in a different pixel than the
+    oracle's; the relative L1 map error is reported.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1005_5198_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1005_5198_amd as rs_mod
+    oracle.build(force=False)
+    return rs_mod
+
+
+def gpu_map(rs, spec, mode):
+    out, st = rs.make_map(spec.params, spec.lens_xy, spec.lens_m, mode=mode, return_stats=True)
+    return out.cpu().numpy(), st
+
+
+def gpu_pix(rs, spec, mode):
+    pix, st = rs.ray_pixels(spec.params, spec.lens_xy, spec.lens_m, mode=mode, return_stats=True)
+    return pix.cpu().numpy().astype(np.int64), st
+
+
+def check_mixed_exact(rs, spec):
+    say("mixed-exact", spec.name, spec.n_rays, "rays", spec.n_lens, "lenses")
+    m_o, st_o = oracle.make_map(spec.params, spec.lens_xy, spec.lens_m)
+    m_g, st_g = gpu_map(rs, spec, "mixed")
+    say("  oracle near-edge rays:", st_o["near_edge"], " re-checked on GPU:", st_g["rays_rechecked"],
+        f"({st_g['rays_rechecked'] / max(spec.n_rays, 1):.4%})")
+    assert np.array_equal(m_g, m_o), f"map differs in {int(np.count_nonzero(m_g != m_o))} pixels"
+    assert st_g["rays_in_map"] == st_o["rays_in_map"]
+    assert st_g["rays_out"] == st_o["rays_out"]
+    assert st_g["rays_singular"] == st_o["rays_singular"]
+    assert st_g["rays_shot"] == spec.n_rays
+    return st_g
+
+
+def check_pixels(rs, spec, fp32_budget=1e-4):
+    say("pixels", spec.name)
+    pix_o, _, _ = oracle.ray_pixels(spec.params, spec.lens_xy, spec.lens_m)
+    pix_m, _ = gpu_pix(rs, spec, "mixed")
+    assert np.array_equal(pix_m, pix_o), f"mixed: {int(np.count_nonzero(pix_m != pix_o))} rays differ"
+    pix_f, _ = gpu_pix(rs, spec, "fp32")
+    changed = np.count_nonzero(pix_f != pix_o) / max(len(pix_o), 1)
+    say(f"  fp32 changed-ray fraction {changed:.3e}")
+    assert changed <= fp32_budget
+    return changed
+
+
+def test_config0_mixed_bit_exact(rs):
+    st = check_mixed_exact(rs, w.config0())
+    assert st["rays_rechecked"] < 0.05 * 1024 * 1024
+
+
+def test_config0_fp32_map_and_pixels(rs):
+    s = w.config0()
+    m_o, _ = oracle.make_map(s.params, s.lens_xy)
+    m_f, st = gpu_map(rs, s, "fp32")
+    rel_l1 = np.abs(m_f.astype(np.int64) - m_o.astype(np.int64)).sum() / m_o.sum()
+    say(f"config0 fp32 relative L1 {rel_l1:.3e}")
+    assert st["rays_rechecked"] == 0
+    assert rel_l1 < 1e-3
+    check_pixels(rs, s)
+
+
+def test_config1_windows(rs):
+    s = w.config1()
+    for (i0, i1, j0, j1) in ((0, 2048, 0, 96), (15000, 17048, 16300, 16700), (30713, 32768, 32700, 32768)):
+        sub = s.window(i0, i1, j0, j1)
+        check_mixed_exact(rs, sub)
+        check_pixels(rs, sub)
+
+
+def test_config2_windows(rs):
+    s = w.config2()
+    for (i0, i1, j0, j1) in ((9000, 10000, 1800, 2040), (0, 700, 0, 64), (18500, 19200, 3790, 3840)):
+        sub = s.window(i0, i1, j0, j1)
+        check_mixed_exact(rs, sub)
+        check_pixels(rs, sub)
+
+
+def test_config2_full_map_sampled(rs):
+    """Full 19200 x 3840-ray map in the launch configuration the benchmark times:
+    conservation, determinism, and sampled rays checked one by one against the oracle."""
+    s = w.config2()
+    say("config2 full map, mixed")
+    xy, m = rs.lens_tensors(s.lens_xy)
+    ws = rs.new_workspace(s.params, s.n_lens, "mixed")
+    out1 = rs.make_map(s.params, xy, None, mode="mixed", workspace=ws)
+    st = rs.read_stats(ws)
+    out2 = rs.make_map(s.params, xy, None, mode="mixed", workspace=ws)
+    st2 = rs.read_stats(ws)
+    a, b = out1.cpu().numpy(), out2.cpu().numpy()
+    assert np.array_equal(a, b) and st == st2
+    assert st["rays_in_map"] + st["rays_out"] + st["rays_singular"] == s.n_rays
+    assert int(a.sum()) == st["rays_in_map"]
+    say(f"  in-map {st['rays_in_map']}, re-checked {st['rays_rechecked']} "
+        f"({st['rays_rechecked'] / s.n_rays:.3%})")
+    # sampled rays: a 64 x 16 window at seeded random places, each ray vs the oracle
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        i0 = int(rng.integers(0, 19200 - 64))
+        j0 = int(rng.integers(0, 3840 - 16))
+        sub = s.window(i0, i0 + 64, j0, j0 + 16)
+        pix_o, _, _ = oracle.ray_pixels(sub.params, sub.lens_xy)
+        pix_m, _ = gpu_pix(rs, sub, "mixed")
+        assert np.array_equal(pix_m, pix_o)
+
+
+def test_windows_sum_to_full_map(rs):
+    """Ray windows are exact partial maps: their sum equals the full map (checkpoint/resume)."""
+    s = w.config0()
+    full, _ = gpu_map(rs, s, "mixed")
+    xy, _ = rs.lens_tensors(s.lens_xy)
+    acc = None
+    for (j0, j1) in ((0, 333), (333, 700), (700, 1024)):
+        sub = s.window(0, 1024, j0, j1)
+        acc = rs.make_map(sub.params, xy, None, mode="mixed", out=acc, accumulate=acc is not None)
+    assert np.array_equal(acc.cpu().numpy(), full)
+
+
+EDGE_CASES = {
+    # name: (sigma_c, gamma, shoot, src, window, n_lens, masses)
+    "no_lenses_identity": (0.0, 0.0, (-20.0, -20.0, 40.0, 40.0, 1024, 1024), (-10.0, -10.0, 20.0, 20.0, 256, 256), None, 0, False),
+    "ragged_window": (0.1, 0.2, (-6.0, -5.0, 12.0, 10.0, 301, 173), (-4.0, -4.0, 8.0, 8.0, 37, 53), (3, 298, 5, 170), 57, False),
+    "single_ray": (0.0, 0.1, (-2.0, -2.0, 4.0, 4.0, 9, 9), (-3.0, -3.0, 6.0, 6.0, 5, 5), (4, 5, 4, 5), 7, False),
+    "masses": (0.05, 0.15, (-8.0, -8.0, 16.0, 16.0, 257, 255), (-6.0, -6.0, 12.0, 12.0, 64, 48), None, 131, True),
+    "negative_parity": (0.7, 0.5, (-30.0, -12.0, 60.0, 24.0, 600, 240), (-8.0, -8.0, 16.0, 16.0, 64, 64), None, 200, False),
+    "one_lens_many_tiles_of_rays": (0.0, 0.0, (-3.0, -3.0, 6.0, 6.0, 700, 500), (-4.0, -4.0, 8.0, 8.0, 128, 128), None, 1, False),
+    "lens_count_not_multiple_of_tile": (0.2, 0.0, (-10.0, -10.0, 20.0, 20.0, 200, 200), (-5.0, -5.0, 10.0, 10.0, 40, 40), None, 2051, False),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE_CASES))
+def test_edge_cases(rs, case):
+    sc, g, shoot, src, window, n, masses = EDGE_CASES[case]
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
+    lens = rng.uniform(-12, 12, size=(n, 2)) if n else np.zeros((0, 2))
+    mm = rng.uniform(0.1, 3.0, size=n) if masses else None
+    p = w.make_params(0.3, sc, g, shoot, src, window)
+    spec = w.MapSpec(case, p, lens, mm)
+    check_mixed_exact(rs, spec)
+    check_pixels(rs, spec, fp32_budget=2e-3 if case == "single_ray" else 1e-4)
+
+
+def test_empty_window(rs):
+    s = w.config0().window(10, 10, 0, 1024)
+    m_g, st = gpu_map(rs, s, "mixed")
+    assert m_g.sum() == 0 and st["rays_shot"] == 0
+
+
+def test_singular_ray_on_lens(rs):
+    """A lens exactly on a grid point: the ray is re-checked and counted as singular."""
+    p = w.make_params(0.0, 0.0, 0.0, (-2.0, -2.0, 4.0, 4.0, 16, 16), (-2.0, -2.0, 4.0, 4.0, 8, 8))
+    lens = np.array([[-0.625, -0.625], [1.3, 0.7]])
+    spec = w.MapSpec("singular", p, lens, None)
+    st = check_mixed_exact(rs, spec)
+    assert st["rays_singular"] == 1
+    pix, _ = gpu_pix(rs, spec, "mixed")
+    assert pix[5 * 16 + 5] == -2
+
+
+def test_gamma_transpose_on_gpu(rs):
+    """Pin 4 through the HIP path: the mixed map is bit-exact, so the symmetry holds on the GPU."""
+    rng = np.random.default_rng(11)
+    lens = rng.uniform(-9, 9, size=(37, 2))
+    p = w.make_params(0.3, 0.15, 0.3, (-7.0, -5.0, 14.0, 10.0, 140, 100), (-3.0, -4.0, 6.0, 8.0, 48, 64))
+    q = w.make_params(0.3, 0.15, -0.3, (-5.0, -7.0, 10.0, 14.0, 100, 140), (-4.0, -3.0, 8.0, 6.0, 64, 48))
+    m1, _ = gpu_map(rs, w.MapSpec("a", p, lens, None), "mixed")
+    m2, _ = gpu_map(rs, w.MapSpec("b", q, lens[:, ::-1].copy(), None), "mixed")
+    assert np.array_equal(m1, m2.T)
+
+
+def test_invalid_arguments_raise(rs):
+    from paper_1005_5198_amd._lib import RayshootError, RS_EINVAL, RS_ENOMEM
+    s = w.config0()
+    bad = dict(s.params)
+    bad["npx"] = 0
+    with pytest.raises(RayshootError) as e:
+        rs.make_map(bad, s.lens_xy)
+    assert e.value.code == RS_EINVAL
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(RayshootError) as e:
+        rs.make_map(s.params, s.lens_xy, workspace=small)
+    assert e.value.code == RS_ENOMEM
