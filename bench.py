@@ -1,0 +1,164 @@
+"""Benchmark: inverse ray-shooting magnification maps on one MI355X.
+
+One step = one whole magnification map of the high-optical-depth workload
+(sigma* = 0.8, gamma = 0.3, 17240 unit lenses in a disc of radius 146.8,
+19200 x 3840 rays at spacing 0.0125 over a 240 x 48 shooting rectangle,
+1024^2-pixel source map of side 20; 1.271e12 ray-lens interactions) in the
+oracle-matching mixed mode (FP32 deflection + FP64 edge re-check).
+Inputs (lenses) are resident in HBM before the timed region.
+
+Prints ONE JSON line:
+  value       ray-lens interactions per second over the timed steps
+  roofline    FP32 VALU roofline of the deflection kernel: algorithmic
+              10 FLOP per interaction / mean kernel duration (HIP events on
+              the kernel's stream), against the 157.3 TFLOP/s FP32 peak
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample
+              of the same map (a band of ray rows)
+Also reported: the plain-FP32 mode rate, the re-check fraction, and the
+batched and served comparisons when --batched/--serve are given.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3       # 256 CU x 2.4 GHz x 128 FP32 lanes x 2 FLOP (FMA)
+FLOP_PER_INTERACTION = 10      # the paper's N_FLOP (Section 2, Phi); one deflection term
+METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batched vs plain"
+
+# HBM traffic of the deflection kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on the
+# same workload, scaled by the copy-kernel calibration factor. None until measured for the
+# current kernel.
+TRAFFIC_BYTES_PER_LAUNCH = 1.043e9   # profiles/shoot_kernel_config2.md (mixed-mode kernel)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="mixed", choices=("mixed", "fp32"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--batched", action="store_true", help="also time the 64-map batch")
+    ap.add_argument("--serve", action="store_true", help="also run the serving loop")
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, target_s: float):
+    """Time the FP64 oracle on a band of ray rows of the same map, all host cores (<= 16)."""
+    import oracle
+    oracle.build(force=False)
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    nx = spec.params["nx"]
+    # calibrate on a thin band, then size the sample to about target_s seconds
+    rows = 24
+    j0 = spec.params["ny"] // 2
+    sub = spec.window(0, nx, j0, j0 + rows)
+    t = time.perf_counter()
+    oracle.make_map(sub.params, sub.lens_xy, sub.lens_m, nthreads=threads)
+    dt = time.perf_counter() - t
+    rate = sub.interactions / max(dt, 1e-6)
+    rows = int(max(4, min(spec.params["ny"] - j0, target_s * rate / (nx * spec.n_lens))))
+    sub = spec.window(0, nx, j0, j0 + rows)
+    t = time.perf_counter()
+    oracle.make_map(sub.params, sub.lens_xy, sub.lens_m, nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": sub.interactions / dt, "unit": "ray·lens/s", "cores": threads, "kind": "oracle",
+            "sample": f"rows {j0}..{j0 + rows} of the {nx}x{spec.params['ny']}-ray map "
+                      f"({sub.n_rays} rays x {spec.n_lens} lenses, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU design shards ray rows and sum-reduces the uint32 maps).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1005_5198_amd as rs
+    from paper_1005_5198_amd import workloads as w
+
+    torch.cuda.set_device(0)
+    spec = w.config2()
+    xy, m = rs.lens_tensors(spec.lens_xy, spec.lens_m)
+    ws = rs.new_workspace(spec.params, spec.n_lens, args.mode)
+    out = torch.empty((spec.params["npy"], spec.params["npx"]), dtype=torch.uint32, device="cuda")
+
+    for _ in range(args.warmup):
+        rs.make_map(spec.params, xy, m, mode=args.mode, out=out, workspace=ws)
+    torch.cuda.synchronize()
+
+    rs.profile_enable(True)
+    rs.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rs.make_map(spec.params, xy, m, mode=args.mode, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, launches, inter_launched = rs.profile_read()
+    rs.profile_enable(False)
+    stats = rs.read_stats(ws)
+
+    inter = spec.interactions
+    value = inter * args.steps / elapsed
+    ms_per_step = elapsed * 1e3 / args.steps
+    achieved_tflops = FLOP_PER_INTERACTION * inter_launched / (kernel_ms * 1e-3) / 1e12
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ray·lens/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded lens disc; no dataset)",
+        "config": {"workload": "config2: sigma*=0.8 gamma=0.3, 17240 unit lenses (R=146.8), "
+                               "19200x3840 rays over 240x48, 1024^2 px source of side 20, "
+                               f"{args.mode} mode",
+                   "rays": spec.n_rays, "lenses": spec.n_lens, "interactions_per_map": inter,
+                   "mode": args.mode},
+        "pct_fp32_peak": FLOP_PER_INTERACTION * value / (FP32_PEAK_TFLOPS * 1e12),
+        "maps_per_s": args.steps / elapsed,
+        "recheck_fraction": stats["rays_rechecked"] / spec.n_rays,
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_PEAK_TFLOPS,
+                     "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                     "kernel": "shoot_kernel (deflection + binning)",
+                     "launches": launches, "mean_launch_ms": kernel_ms / max(launches, 1)},
+    }
+    if args.mode == "mixed":
+        # the plain-FP32 mode on the same map, for comparison
+        ws32 = rs.new_workspace(spec.params, spec.n_lens, "fp32")
+        rs.make_map(spec.params, xy, m, mode="fp32", out=out, workspace=ws32)
+        torch.cuda.synchronize()
+        n32 = max(2, args.steps // 2)
+        t = time.perf_counter()
+        for _ in range(n32):
+            rs.make_map(spec.params, xy, m, mode="fp32", out=out, workspace=ws32)
+        torch.cuda.synchronize()
+        result["fp32_mode_value"] = inter * n32 / (time.perf_counter() - t)
+    if args.batched or args.serve:
+        from paper_1005_5198_amd import bench_extra
+        if args.batched:
+            result["batched"] = bench_extra.batched(rs)
+        if args.serve:
+            result["served"] = bench_extra.served(rs)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -31,7 +31,7 @@ constexpr int NEAR_MAX = 64;                  // per-block list of lenses close 
 // Workspace layout (bytes).
 constexpr size_t WS_COUNTERS = 0;             // uint64 [8]: in, out, singular, rechecked, spare
 constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] queue lengths
-constexpr int64_t CHUNK_RAYS = int64_t(1) << 26;  // rays per launch (queue capacity)
+constexpr int64_t CHUNK_RAYS = int64_t(1) << 27;  // rays per launch (queue capacity)
 
 enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3 };
 

@@ -50,9 +50,9 @@ def test_workspace_bytes_and_validation(lib):
     n_mixed = api.workspace_bytes(s.params, s.n_lens, "mixed")
     n_fp32 = api.workspace_bytes(s.params, s.n_lens, "fp32")
     assert n_fp32 < n_mixed
-    # the mixed queue holds one launch's rays: whole 32-row bands of the window, at most 2^26 rays
-    rows = (1 << 26) // 19200 // 32 * 32
-    assert n_mixed >= 4 * rows * 19200 and n_mixed < 4 * (1 << 26) + 65536
+    # the mixed queue holds one launch's rays: whole 32-row bands of the window, at most 2^27 rays
+    rows = (1 << 27) // 19200 // 32 * 32
+    assert n_mixed >= 4 * rows * 19200 and n_mixed < 4 * (1 << 27) + 65536
     bad = dict(s.params)
     bad["i1"] = bad["nx"] + 1
     c = api.to_params(bad)
