@@ -23,7 +23,10 @@
  *             rigorous bound on its source-position error, and rays whose
  *             bound reaches a pixel edge are re-evaluated in FP64 with the
  *             plain definition (lens order, no fused multiply-add, IEEE
- *             division). The count map equals the FP64 definition's map.
+ *             division). A first FP64 stage with fused multiply-adds and a
+ *             rigorous bound decides almost every queued ray; only rays it
+ *             cannot place run the exact sequence. The count map equals the
+ *             FP64 definition's map.
  *   RS_FP32   the same FP32 sum, binned directly (no bound, no re-check).
  *
  * Conventions for every call:
@@ -58,7 +61,9 @@ extern "C" {
 #define RS_FP32 0
 #define RS_MIXED 1
 
-#define RS_ACCUMULATE 1    /* flag: add to the map instead of zeroing it first */
+#define RS_ACCUMULATE 1      /* flag: add to the map instead of zeroing it first */
+#define RS_EXACT_RECHECK 2   /* flag (RS_MIXED): re-check every queued ray with the definition's exact
+                                FP64 sequence only, skipping the faster bounded FP64 first stage */
 
 /* One map: macro model, shooting grid, ray window and source grid. */
 typedef struct {
@@ -73,7 +78,7 @@ typedef struct {
     double tw, th;          /* source map width and height, > 0 */
     int64_t npx, npy;       /* source pixels, > 0; the map is uint32 [npy][npx] row-major */
     int32_t mode;           /* RS_FP32 or RS_MIXED */
-    int32_t flags;          /* 0 or RS_ACCUMULATE */
+    int32_t flags;          /* 0 or an OR of RS_ACCUMULATE, RS_EXACT_RECHECK */
 } rs_map_params;
 
 /* Counters of one map (or window), accumulated on the device. */
@@ -139,6 +144,48 @@ int rs_read_stats(const void *workspace, rs_map_stats *stats_host, void *stream)
  */
 int rs_profile_enable(int on);
 int rs_profile_read(double *kernel_ms, int64_t *launches, double *interactions);
+
+/* ------------------------------------------------------------------------- */
+/* Autotuner of the deflection kernel's thread shape.                        */
+/* The paper notes that the direct GPU code's batch and thread-group sizes    */
+/* are hardware dependent (Section 2, GPU-D); here the choice is measured.    */
+/* Every shape covers the same 64 x 32 ray patch per block, so the choice     */
+/* changes speed only: maps are bit-identical across shapes in both modes.    */
+/* ------------------------------------------------------------------------- */
+
+#define RS_MAX_SHAPES 8
+
+typedef struct {
+    int32_t shape;               /* fastest shape id on the sample */
+    int32_t n_shapes;            /* shapes available */
+    int32_t rays_per_lane[RS_MAX_SHAPES][2];  /* (x, y) rays per lane of each shape */
+    int32_t threads[RS_MAX_SHAPES];           /* threads per block of each shape */
+    double ms[RS_MAX_SHAPES];    /* deflection-kernel time of each shape on the sample, ms */
+    double sample_interactions;  /* ray-lens interactions in the sample */
+} rs_tune_result;
+
+/*
+ * Time every shape on a sample of this map (a band of rows from the middle of
+ * the window holding about sample_rays rays; <= 0 picks 2^22) and remember the
+ * fastest for maps with the same signature (mode, unit or general masses,
+ * N* rounded to a power of two). Later rs_make_map calls with that signature
+ * use it. scratch_map (device, uint32 [npy][npx]) is overwritten. Synchronises
+ * the stream. Errors as rs_make_map.
+ */
+int rs_tune(const rs_map_params *params, const double *lens_xy, const double *lens_m, int64_t n_lens,
+            uint32_t *scratch_map, void *workspace, size_t workspace_bytes, int64_t sample_rays,
+            void *stream, rs_tune_result *result_host);
+
+/*
+ * Force a shape for every later launch (0 .. n_shapes-1), or -1 to use the
+ * tuner's cache and the built-in default. The previous setting is stored in
+ * *previous when it is not NULL. Errors: RS_EINVAL (shape out of range).
+ */
+int rs_set_shape(int shape, int *previous);
+
+/* Write / read the tuner's cache as text (one "mode unit n_bucket shape" line each). */
+int rs_tune_save(const char *path);
+int rs_tune_load(const char *path);
 
 #ifdef __cplusplus
 }

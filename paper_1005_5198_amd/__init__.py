@@ -11,7 +11,8 @@ Public entry points (loaded lazily so that importing the package, e.g. for
 ``paper_1005_5198_amd.workloads.make_params`` builds one.
 """
 _API = ("make_map", "ray_pixels", "read_stats", "workspace_bytes", "new_workspace", "to_params",
-        "lens_tensors", "profile_enable", "profile_read", "version")
+        "lens_tensors", "profile_enable", "profile_read", "version", "tune", "set_shape", "tune_save",
+        "tune_load")
 
 
 def __getattr__(name):

@@ -20,6 +20,7 @@ RS_ECANCELED = -5
 RS_FP32 = 0
 RS_MIXED = 1
 RS_ACCUMULATE = 1
+RS_EXACT_RECHECK = 2
 
 _ERRNAMES = {RS_EINVAL: "RS_EINVAL", RS_ENOMEM: "RS_ENOMEM", RS_EHIP: "RS_EHIP",
              RS_EBUSY: "RS_EBUSY", RS_ECANCELED: "RS_ECANCELED"}
@@ -53,6 +54,12 @@ class MapStats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("n_shapes", ctypes.c_int32),
+                ("rays_per_lane", (ctypes.c_int32 * 2) * 8), ("threads", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_double * 8), ("sample_interactions", ctypes.c_double)]
+
+
 _lib = None
 
 VP = ctypes.c_void_p
@@ -72,6 +79,10 @@ def _declare(lib):
         "rs_read_stats": ([VP, P(MapStats), VP], INT),
         "rs_profile_enable": ([INT], INT),
         "rs_profile_read": ([P(ctypes.c_double), P(I64), P(ctypes.c_double)], INT),
+        "rs_tune": ([P(MapParams), VP, VP, I64, VP, VP, SZ, I64, VP, P(TuneResult)], INT),
+        "rs_set_shape": ([INT, ctypes.POINTER(INT)], INT),
+        "rs_tune_save": ([ctypes.c_char_p], INT),
+        "rs_tune_load": ([ctypes.c_char_p], INT),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -100,4 +111,5 @@ def check(rc: int) -> None:
 def exported_symbols():
     """Names of the C-ABI functions this binding declares."""
     return ["rs_version", "rs_last_error", "rs_workspace_bytes", "rs_make_map", "rs_ray_pixels",
-            "rs_read_stats", "rs_profile_enable", "rs_profile_read"]
+            "rs_read_stats", "rs_profile_enable", "rs_profile_read", "rs_tune", "rs_set_shape",
+            "rs_tune_save", "rs_tune_load"]

@@ -17,7 +17,7 @@ from . import _lib as L
 MODES = {"fp32": L.RS_FP32, "mixed": L.RS_MIXED}
 
 
-def to_params(p: dict, mode: str = "mixed", accumulate: bool = False) -> L.MapParams:
+def to_params(p: dict, mode: str = "mixed", accumulate: bool = False, exact_recheck: bool = False) -> L.MapParams:
     """Build the C parameter struct from a workloads-style dict (keys of MapParams)."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {sorted(MODES)}")
@@ -26,7 +26,7 @@ def to_params(p: dict, mode: str = "mixed", accumulate: bool = False) -> L.MapPa
         if name == "mode":
             s.mode = MODES[mode]
         elif name == "flags":
-            s.flags = L.RS_ACCUMULATE if accumulate else 0
+            s.flags = (L.RS_ACCUMULATE if accumulate else 0) | (L.RS_EXACT_RECHECK if exact_recheck else 0)
         else:
             setattr(s, name, p[name])
     return s
@@ -73,7 +73,7 @@ def new_workspace(params: dict, n_lens: int, mode: str = "mixed", device=None) -
 
 def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optional[torch.Tensor] = None,
              workspace: Optional[torch.Tensor] = None, accumulate: bool = False, stream=None,
-             return_stats: bool = False):
+             return_stats: bool = False, exact_recheck: bool = False):
     """Count map uint32 [npy, npx] of the params' ray window (Section 2, Eq. (sigma), Eq. (mu_ij)).
 
     Asynchronous on the stream unless return_stats is set (then it synchronises
@@ -81,7 +81,7 @@ def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optio
     """
     dev = _device()
     xy, m = lens_tensors(lens_xy, lens_m, dev)
-    c = to_params(params, mode, accumulate)
+    c = to_params(params, mode, accumulate, exact_recheck)
     if out is None:
         out = torch.empty((int(params["npy"]), int(params["npx"])), dtype=torch.uint32, device=dev)
     if out.dtype != torch.uint32 or not out.is_contiguous() or tuple(out.shape) != (c.npy, c.npx):
@@ -97,11 +97,11 @@ def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optio
 
 
 def ray_pixels(params: dict, lens_xy, lens_m=None, mode: str = "mixed", workspace=None, stream=None,
-               return_stats: bool = False):
+               return_stats: bool = False, exact_recheck: bool = False):
     """Per-ray pixel index int32 over the window (row-major): v*npx+u, -1 out, -2 singular."""
     dev = _device()
     xy, m = lens_tensors(lens_xy, lens_m, dev)
-    c = to_params(params, mode)
+    c = to_params(params, mode, exact_recheck=exact_recheck)
     n = int((params["i1"] - params["i0"]) * (params["j1"] - params["j0"]))
     pix = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     if workspace is None:
@@ -135,3 +135,35 @@ def profile_read():
 
 def version() -> str:
     return L.lib().rs_version().decode()
+
+
+def tune(params: dict, lens_xy, lens_m=None, mode: str = "mixed", sample_rays: int = 1 << 22, stream=None) -> dict:
+    """Time every thread shape of the deflection kernel on a sample of this map; cache the fastest."""
+    dev = _device()
+    xy, m = lens_tensors(lens_xy, lens_m, dev)
+    c = to_params(params, mode)
+    scratch = torch.empty((c.npy, c.npx), dtype=torch.uint32, device=dev)
+    ws = new_workspace(params, xy.shape[0], mode, dev)
+    r = L.TuneResult()
+    L.check(L.lib().rs_tune(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], scratch.data_ptr(), ws.data_ptr(),
+                            ws.numel(), int(sample_rays), _stream_handle(stream), ctypes.byref(r)))
+    shapes = [dict(shape=k, rays_per_lane=(r.rays_per_lane[k][0], r.rays_per_lane[k][1]),
+                   threads=r.threads[k], ms=r.ms[k],
+                   interactions_per_s=r.sample_interactions / (r.ms[k] * 1e-3) if r.ms[k] > 0 else 0.0)
+              for k in range(r.n_shapes)]
+    return dict(best=r.shape, shapes=shapes, sample_interactions=r.sample_interactions)
+
+
+def set_shape(shape: int) -> int:
+    """Force a thread shape (or -1 for tuned/default); returns the previous setting."""
+    prev = ctypes.c_int(0)
+    L.check(L.lib().rs_set_shape(int(shape), ctypes.byref(prev)))
+    return prev.value
+
+
+def tune_save(path: str) -> None:
+    L.check(L.lib().rs_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    L.check(L.lib().rs_tune_load(path.encode()))

@@ -7,20 +7,18 @@
 
 namespace rs {
 
-// Thread shape of the deflection kernel. A block is 2x2 waves; a wave is 8x8
-// lanes; a lane owns RX x RY rays. Rays of one lane share their y (per row)
-// and x (per column) offsets, so dy and dy^2 are computed once per lens and row.
-constexpr int RX = 4;
-constexpr int RY = 2;
+// Ray patch of one block of the deflection kernel: PATCH_X x PATCH_Y rays,
+// lanes laid out 8 x 8 per wave. The thread shape (rays per lane, waves per
+// block) is a tunable choice among N_SHAPES that all cover the same patch.
 constexpr int LANES_X = 8;
 constexpr int LANES_Y = 8;
-constexpr int WAVES_X = 2;
-constexpr int WAVES_Y = 2;
-constexpr int BLOCK_THREADS = 64 * WAVES_X * WAVES_Y;
-constexpr int STRIDE_X = LANES_X * WAVES_X;   // ray-index distance between a lane's columns
-constexpr int STRIDE_Y = LANES_Y * WAVES_Y;   // ray-index distance between a lane's rows
-constexpr int PATCH_X = RX * STRIDE_X;        // rays per block along x (64)
-constexpr int PATCH_Y = RY * STRIDE_Y;        // rays per block along y (32)
+constexpr int PATCH_X = 64;
+constexpr int PATCH_Y = 32;
+constexpr int N_SHAPES = 4;
+struct ShapeInfo {
+    int rx, ry, wx, wy;   // rays per lane along x, y; waves per block along x, y
+};
+const ShapeInfo &shape_info(int shape);
 
 // Lenses staged into LDS per tile, and lenses per FP32 partial sum before it
 // is folded into the FP64 accumulator.
@@ -73,13 +71,13 @@ struct RecheckArgs {
     uint32_t *map;
     int32_t *pix_out;
     unsigned long long *counters;
-    const uint32_t *queue;
+    uint32_t *queue;       // stage A marks unresolved entries in place
     const uint32_t *qcount;
 };
 
 hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_qcount,
                        hipStream_t stream);
-hipError_t launch_shoot(const ShootArgs &a, int mode, hipStream_t stream);
-hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, hipStream_t stream);
+hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream);
+hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);
 
 }  // namespace rs

@@ -57,7 +57,7 @@ int validate(const rs_map_params *p, int64_t n_lens) {
     if (p->nx >= (int64_t(1) << 52) || p->ny >= (int64_t(1) << 52)) return fail(RS_EINVAL, "ray grid too large");
     if (p->i1 - p->i0 > (int64_t(1) << 26)) return fail(RS_EINVAL, "window wider than 2^26 rays");
     if (p->mode != RS_FP32 && p->mode != RS_MIXED) return fail(RS_EINVAL, "mode must be RS_FP32 or RS_MIXED");
-    if (p->flags & ~RS_ACCUMULATE) return fail(RS_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(RS_ACCUMULATE | RS_EXACT_RECHECK)) return fail(RS_EINVAL, "unknown flags 0x%x", p->flags);
     if (n_lens < 0) return fail(RS_EINVAL, "n_lens < 0");
     return RS_OK;
 }
@@ -88,9 +88,14 @@ struct Profile {
 };
 static Profile g_prof;
 
+int choose_shape(int mode, bool unit, int64_t n_lens);
+
 // Enqueue the whole map (or pixel) computation. map may be null when pix is set.
+// shape < 0 picks the tuned or default thread shape. When kernel_ms is given,
+// the deflection launches are timed with events and the call synchronises.
 int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
-                uint32_t *map, int32_t *pix, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                uint32_t *map, int32_t *pix, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                int shape, float *kernel_ms) {
     int rc = validate(p, n_lens);
     if (rc) return rc;
     if (n_lens > 0 && !lens_xy) return fail(RS_EINVAL, "lens_xy is NULL");
@@ -164,6 +169,14 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         std::lock_guard<std::mutex> lk(g_prof.mu);
         prof = g_prof.on;
     }
+    if (shape < 0) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
+    hipEvent_t t_first = nullptr, t_last = nullptr;
+    if (kernel_ms) {
+        *kernel_ms = 0.0f;
+        if (hipEventCreate(&t_first) != hipSuccess || hipEventCreate(&t_last) != hipSuccess)
+            return fail(RS_EHIP, "hipEventCreate failed");
+    }
+    float timed_ms = 0.0f;
     for (int64_t c = 0; c < pl.n_chunks; ++c) {
         a.jc0 = p->j0 + c * pl.rows_per_chunk;
         a.jc1 = a.jc0 + pl.rows_per_chunk < p->j1 ? a.jc0 + pl.rows_per_chunk : p->j1;
@@ -174,8 +187,16 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
                 return fail(RS_EHIP, "hipEventCreate failed");
             if (hipEventRecord(ev0, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
         }
-        e = launch_shoot(a, p->mode, stream);
+        if (kernel_ms && hipEventRecord(t_first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
+        e = launch_shoot(a, p->mode, shape, stream);
         if (e != hipSuccess) return hip_fail(e, "deflection kernel");
+        if (kernel_ms) {
+            float ms = 0.0f;
+            if (hipEventRecord(t_last, stream) != hipSuccess || hipEventSynchronize(t_last) != hipSuccess ||
+                hipEventElapsedTime(&ms, t_first, t_last) != hipSuccess)
+                return fail(RS_EHIP, "timing the deflection kernel failed");
+            timed_ms += ms;
+        }
         if (prof) {
             if (hipEventRecord(ev1, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
             std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -184,9 +205,15 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         if (p->mode == RS_MIXED) {
             r.jc0 = a.jc0;
             r.qcount = a.qcount;
-            e = launch_recheck(r, (a.jc1 - a.jc0) * pl.W, stream);
+            e = launch_recheck(r, (a.jc1 - a.jc0) * pl.W, (p->flags & RS_EXACT_RECHECK) != 0, stream);
             if (e != hipSuccess) return hip_fail(e, "re-check kernel");
         }
+    }
+    if (kernel_ms) {
+        *kernel_ms = timed_ms;
+        (void)hipEventDestroy(t_first);
+        (void)hipEventDestroy(t_last);
+        if (hipStreamSynchronize(stream) != hipSuccess) return fail(RS_EHIP, "hipStreamSynchronize failed");
     }
     return RS_OK;
 }
@@ -210,14 +237,14 @@ int rs_make_map(const rs_map_params *params, const double *lens_xy, const double
                 uint32_t *map, void *workspace, size_t workspace_bytes, void *stream) {
     if (!map) return fail(RS_EINVAL, "map is NULL");
     return enqueue_map(params, lens_xy, lens_m, n_lens, map, nullptr, workspace, workspace_bytes,
-                       static_cast<hipStream_t>(stream));
+                       static_cast<hipStream_t>(stream), -1, nullptr);
 }
 
 int rs_ray_pixels(const rs_map_params *params, const double *lens_xy, const double *lens_m, int64_t n_lens,
                   int32_t *pix, void *workspace, size_t workspace_bytes, void *stream) {
     if (!pix) return fail(RS_EINVAL, "pix is NULL");
     return enqueue_map(params, lens_xy, lens_m, n_lens, nullptr, pix, workspace, workspace_bytes,
-                       static_cast<hipStream_t>(stream));
+                       static_cast<hipStream_t>(stream), -1, nullptr);
 }
 
 int rs_read_stats(const void *workspace, rs_map_stats *stats_host, void *stream) {

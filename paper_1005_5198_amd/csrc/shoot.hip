@@ -10,9 +10,10 @@
 //    of LENS_TILE, converted once per block from FP64 to FP32 offsets relative
 //    to the patch centre, so FP32 carries small numbers and the per-block
 //    conversion is paid once per lens per 2048 rays.
-//  * Each lane owns 4 x 2 rays; per lens it computes dx for 4 columns and dy,
-//    dy^2 for 2 rows, then r^2 = fma(dx, dx, dy^2), v_rcp_f32, and two FMAs
-//    per ray. Every LDS read is a 16-byte broadcast of two lenses.
+//  * Each lane owns RX x RY rays (4x2, 4x4, 8x2 or 8x4: a tuned choice); per
+//    lens it computes dx for RX columns and dy, dy^2 for RY rows, then
+//    r^2 = fma(dx, dx, dy^2), v_rcp_f32, and two FMAs per ray. Every LDS read
+//    is a 16-byte broadcast of two lenses.
 //  * The sum runs in FP32 over GROUP lenses, then each partial is folded
 //    exactly into an FP64 accumulator, so FP32 rounding never sees the large
 //    running total.
@@ -68,8 +69,15 @@ __device__ __forceinline__ void aggregated_add(uint32_t *map, int p) {
     }
 }
 
-template <bool UNIT, int MODE, bool PIX>
-__global__ __launch_bounds__(BLOCK_THREADS) void shoot_kernel(const ShootArgs a) {
+// RX x RY rays per lane, WX x WY waves per block; every shape covers the same
+// PATCH_X x PATCH_Y ray patch, so a ray's arithmetic (patch origin, lens
+// offsets, operation order) does not depend on the shape chosen.
+template <int RX, int RY, int WX, int WY, bool UNIT, int MODE, bool PIX>
+__global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) {
+    constexpr int BLOCK_THREADS = 64 * WX * WY;
+    constexpr int STRIDE_X = LANES_X * WX;
+    constexpr int STRIDE_Y = LANES_Y * WY;
+    static_assert(RX * STRIDE_X == PATCH_X && RY * STRIDE_Y == PATCH_Y, "shape must tile the patch");
     __shared__ float4 tile[LENS_TILE];        // UNIT: two (x,y) pairs per float4; else (x,y,m,0)
     __shared__ NearLens near_list[NEAR_MAX];
     __shared__ int near_count;
@@ -78,7 +86,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void shoot_kernel(const ShootArgs a)
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int wx = wave % WAVES_X, wy = wave / WAVES_X;
+    const int wx = wave % WX, wy = wave / WX;
     const int lx = lane % LANES_X, ly = lane / LANES_X;
 
     // Patch of this block.
@@ -94,19 +102,15 @@ __global__ __launch_bounds__(BLOCK_THREADS) void shoot_kernel(const ShootArgs a)
     const double h = sqrt(hx * hx + hy * hy);
     const double near_r2 = 4.0 * h * h;
 
-    // This lane's rays: FP32 offsets from the patch origin.
+    // This lane's rays: column i = i_lane + c * STRIDE_X, row j = j_lane + r * STRIDE_Y,
+    // held as FP32 offsets from the patch origin.
+    const int64_t i_lane = ib + wx * LANES_X + lx;
+    const int64_t j_lane = jb + wy * LANES_Y + ly;
     float rxl[RX], ryl[RY];
-    int64_t ri[RX], rj[RY];
 #pragma unroll
-    for (int c = 0; c < RX; ++c) {
-        ri[c] = ib + c * STRIDE_X + wx * LANES_X + lx;
-        rxl[c] = (float)(ray_coord(a.sx0, ri[c], a.spx) - ox);
-    }
+    for (int c = 0; c < RX; ++c) rxl[c] = (float)(ray_coord(a.sx0, i_lane + c * STRIDE_X, a.spx) - ox);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        rj[r] = jb + r * STRIDE_Y + wy * LANES_Y + ly;
-        ryl[r] = (float)(ray_coord(a.sy0, rj[r], a.spy) - oy);
-    }
+    for (int r = 0; r < RY; ++r) ryl[r] = (float)(ray_coord(a.sy0, j_lane + r * STRIDE_Y, a.spy) - oy);
 
     double Ax[RY][RX], Ay[RY][RX];
 #pragma unroll
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void shoot_kernel(const ShootArgs a)
     for (int r = 0; r < RY; ++r)
 #pragma unroll
         for (int c = 0; c < RX; ++c) {
-            const int64_t i = ri[c], j = rj[r];
+            const int64_t i = i_lane + c * STRIDE_X, j = j_lane + r * STRIDE_Y;
             const bool valid = (i < a.i1) && (j < a.jc1);
             const double x1 = ray_coord(a.sx0, i, a.spx);
             const double x2 = ray_coord(a.sy0, j, a.spy);
@@ -364,14 +368,12 @@ hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_
     return hipGetLastError();
 }
 
-hipError_t launch_shoot(const ShootArgs &a, int mode, hipStream_t stream) {
-    const int64_t nby = (a.jc1 - a.jc0 + PATCH_Y - 1) / PATCH_Y;
-    const int64_t blocks = a.nbx * nby;
-    if (blocks <= 0) return hipSuccess;
+template <int RX, int RY, int WX, int WY>
+static void launch_shape(const ShootArgs &a, int mode, dim3 grid, hipStream_t stream) {
     const bool unit = a.lens_m == nullptr;
     const bool pix = a.pix_out != nullptr;
-    const dim3 grid((unsigned)blocks), block(BLOCK_THREADS);
-#define RS_LAUNCH(U, M, P) hipLaunchKernelGGL((shoot_kernel<U, M, P>), grid, block, 0, stream, a)
+    const dim3 block(64 * WX * WY);
+#define RS_LAUNCH(U, M, P) hipLaunchKernelGGL((shoot_kernel<RX, RY, WX, WY, U, M, P>), grid, block, 0, stream, a)
     if (mode == 0) {
         if (unit) { if (pix) RS_LAUNCH(true, 0, true); else RS_LAUNCH(true, 0, false); }
         else { if (pix) RS_LAUNCH(false, 0, true); else RS_LAUNCH(false, 0, false); }
@@ -380,6 +382,26 @@ hipError_t launch_shoot(const ShootArgs &a, int mode, hipStream_t stream) {
         else { if (pix) RS_LAUNCH(false, 1, true); else RS_LAUNCH(false, 1, false); }
     }
 #undef RS_LAUNCH
+}
+
+const ShapeInfo &shape_info(int shape) {
+    static const ShapeInfo table[N_SHAPES] = {
+        {4, 2, 2, 2}, {4, 4, 2, 1}, {8, 2, 1, 2}, {8, 4, 1, 1},
+    };
+    return table[(shape >= 0 && shape < N_SHAPES) ? shape : 0];
+}
+
+hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream) {
+    const int64_t nby = (a.jc1 - a.jc0 + PATCH_Y - 1) / PATCH_Y;
+    const int64_t blocks = a.nbx * nby;
+    if (blocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks);
+    switch (shape) {
+        case 1: launch_shape<4, 4, 2, 1>(a, mode, grid, stream); break;
+        case 2: launch_shape<8, 2, 1, 2>(a, mode, grid, stream); break;
+        case 3: launch_shape<8, 4, 1, 1>(a, mode, grid, stream); break;
+        default: launch_shape<4, 2, 2, 2>(a, mode, grid, stream); break;
+    }
     return hipGetLastError();
 }
 

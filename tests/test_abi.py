@@ -52,7 +52,7 @@ def test_workspace_bytes_and_validation(lib):
     assert n_fp32 < n_mixed
     # the mixed queue holds one launch's rays: whole 32-row bands of the window, at most 2^27 rays
     rows = (1 << 27) // 19200 // 32 * 32
-    assert n_mixed >= 4 * rows * 19200 and n_mixed < 4 * (1 << 27) + 65536
+    assert n_mixed >= 4 * min(rows, 3840) * 19200 and n_mixed < 4 * (1 << 27) + 65536
     bad = dict(s.params)
     bad["i1"] = bad["nx"] + 1
     c = api.to_params(bad)
@@ -80,3 +80,25 @@ def test_make_map_rejects_null_outputs(lib):
     assert lib.rs_make_map(ctypes.byref(c), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None) == _lib.RS_EINVAL
     assert lib.rs_make_map(ctypes.byref(c), None, None, 5, ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30,
                            None) == _lib.RS_EINVAL
+
+
+def test_tune_cache_file_validation(lib, tmp_path):
+    from paper_1005_5198_amd import api, _lib
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 1 9 77\n")
+    with pytest.raises(_lib.RayshootError):
+        api.tune_load(str(bad))
+    good = tmp_path / "good.txt"
+    good.write_text("1 1 9 2\n0 1 14 1\n")
+    api.tune_load(str(good))
+    out = tmp_path / "out.txt"
+    api.tune_save(str(out))
+    assert "1 1 9 2" in out.read_text()
+
+
+def test_set_shape_range(lib):
+    from paper_1005_5198_amd import api, _lib
+    with pytest.raises(_lib.RayshootError):
+        api.set_shape(99)
+    prev = api.set_shape(2)
+    assert api.set_shape(prev) == 2

@@ -207,3 +207,51 @@ def test_invalid_arguments_raise(rs):
     with pytest.raises(RayshootError) as e:
         rs.make_map(s.params, s.lens_xy, workspace=small)
     assert e.value.code == RS_ENOMEM
+
+
+def test_exact_only_recheck_matches_two_stage(rs):
+    """The two re-check paths (bounded FP64 stage + exact stage, or exact only) give the same map,
+    and both equal the oracle's."""
+    s = w.config2().window(4000, 5200, 1000, 1240)
+    m_o, _ = oracle.make_map(s.params, s.lens_xy)
+    a, sa = rs.make_map(s.params, s.lens_xy, mode="mixed", return_stats=True)
+    b, sb = rs.make_map(s.params, s.lens_xy, mode="mixed", return_stats=True, exact_recheck=True)
+    say(f"re-checked {sa['rays_rechecked']} (two-stage) / {sb['rays_rechecked']} (exact only)")
+    assert sa["rays_rechecked"] == sb["rays_rechecked"] > 0
+    assert np.array_equal(a.cpu().numpy(), m_o) and np.array_equal(b.cpu().numpy(), m_o)
+    pa = rs.ray_pixels(s.params, s.lens_xy, mode="mixed").cpu().numpy()
+    pb = rs.ray_pixels(s.params, s.lens_xy, mode="mixed", exact_recheck=True).cpu().numpy()
+    assert np.array_equal(pa, pb)
+
+
+def test_every_shape_gives_the_same_maps(rs):
+    """All thread shapes cover the same ray patch, so each ray's arithmetic is the same:
+    FP32 maps are bit-identical across shapes, and mixed maps equal the oracle for every shape."""
+    s = w.config2().window(7000, 8300, 2000, 2200)
+    m_o, _ = oracle.make_map(s.params, s.lens_xy)
+    xy, _ = rs.lens_tensors(s.lens_xy)
+    fp32_maps = []
+    try:
+        for shape in range(4):
+            rs.set_shape(shape)
+            say("shape", shape)
+            fp32_maps.append(rs.make_map(s.params, xy, mode="fp32").cpu().numpy())
+            assert np.array_equal(rs.make_map(s.params, xy, mode="mixed").cpu().numpy(), m_o)
+    finally:
+        rs.set_shape(-1)
+    for m in fp32_maps[1:]:
+        assert np.array_equal(m, fp32_maps[0])
+
+
+def test_tuner_picks_and_persists(rs, tmp_path):
+    s = w.config0()
+    res = rs.tune(s.params, s.lens_xy, mode="mixed", sample_rays=1 << 18)
+    say("tune:", res)
+    assert 0 <= res["best"] < len(res["shapes"])
+    assert all(sh["ms"] > 0 for sh in res["shapes"])
+    assert res["shapes"][res["best"]]["ms"] == min(sh["ms"] for sh in res["shapes"])
+    path = str(tmp_path / "tune.txt")
+    rs.tune_save(path)
+    rs.tune_load(path)
+    text = open(path).read().split()
+    assert len(text) % 4 == 0 and len(text) >= 4
