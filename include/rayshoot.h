@@ -187,6 +187,106 @@ int rs_set_shape(int shape, int *previous);
 int rs_tune_save(const char *path);
 int rs_tune_load(const char *path);
 
+/* ------------------------------------------------------------------------- */
+/* Batched maps: many maps, each with its own lenses, grids and parameters,   */
+/* in one persistent launch of the deflection kernel followed by one batched  */
+/* FP64 re-check. Every map is bit-identical to what rs_make_map gives for it. */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    rs_map_params params;    /* one map; every request of a batch has the same mode */
+    const double *lens_xy;   /* device, float64 [n_lens][2] */
+    const double *lens_m;    /* device, float64 [n_lens] or NULL (unit masses) */
+    int64_t n_lens;
+    uint32_t *map;           /* device, uint32 [npy][npx]; zeroed unless params.flags has RS_ACCUMULATE */
+} rs_map_request;
+
+/*
+ * Workspace bytes for this batch: descriptors, counters, and two bits per ray
+ * (rays to re-check, rays left to the exact stage). Returns 0 if a request is
+ * invalid.
+ */
+size_t rs_batch_workspace_bytes(const rs_map_request *requests, int32_t n);
+
+/*
+ * Build n maps (1 <= n <= 65536) in one launch sequence on the stream: one
+ * persistent deflection launch over the 64 x 32-ray patches of every map (most
+ * expensive maps first), then one batched FP64 re-check. Each map's window must
+ * hold fewer than 2^32 rays. The per-map counters stay in the workspace (read
+ * them with rs_batch_read_stats). The library copies its work descriptors from
+ * host memory into the workspace (hipMemcpyAsync) before returning.
+ * Errors: RS_EINVAL (a bad request, mixed modes), RS_ENOMEM (workspace too
+ * small), RS_EHIP.
+ */
+int rs_make_maps(const rs_map_request *requests, int32_t n, void *workspace, size_t workspace_bytes,
+                 void *stream);
+
+/* Counters of each map of the last rs_make_maps on this workspace, in request order. Synchronises. */
+int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_host, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Request loop with continuous batching.                                      */
+/* A scheduler thread admits requests in arrival order when a slot is free and */
+/* their device footprint (lenses, masses, map) fits the server's pool, and    */
+/* keeps two launch steps in flight: each step gives every active request one  */
+/* band of ray rows and runs them all as one rs_make_maps batch. A request that */
+/* arrives while the GPU is busy joins the next step. Each finished map equals  */
+/* rs_make_map of the same request bit for bit (a map is the integer sum of its */
+/* bands).                                                                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* device pool for admitted requests (allocated once, by the server) */
+    int32_t max_inflight;     /* requests admitted at once (slots), >= 1 */
+    int32_t mode;             /* RS_FP32 or RS_MIXED, for every request */
+    double slice_ms;          /* target GPU time of one launch step; <= 0 selects 20 ms */
+} rs_server_cfg;
+
+typedef struct {
+    uint64_t completed, canceled, failed;  /* finished requests by outcome */
+    uint64_t steps;                        /* launch steps run */
+    uint64_t waiting, active, max_waiting; /* queue depths (now, and the largest seen) */
+    uint64_t hbm_in_use_bytes, hbm_peak_bytes;  /* pool bytes held by admitted requests */
+    double interactions;                   /* ray-lens pairs computed */
+    double gpu_busy_s;                     /* summed step time on the device */
+    double maps_per_s;                     /* completed / (last completion - first submission) */
+    double latency_p50_s, latency_p99_s;   /* submission -> map in host memory, completed requests */
+    double latency_mean_s, latency_max_s;
+} rs_server_stats;
+
+typedef struct rs_server rs_server;
+
+/* Start a server on the current device: allocates its pool and two streams, starts its thread. */
+int rs_server_create(const rs_server_cfg *cfg, rs_server **server);
+
+/*
+ * Queue one map. The parameters and the HOST lens arrays are copied before the
+ * call returns; map_host (HOST, uint32 [npy][npx], or NULL to discard) must stay
+ * valid until rs_server_wait returns for the ticket. The window must hold fewer
+ * than 2^32 rays. Errors: RS_EINVAL, RS_ECANCELED (server stopping).
+ */
+int rs_server_submit(rs_server *server, const rs_map_params *params, const double *lens_xy_host,
+                     const double *lens_m_host, int64_t n_lens, uint32_t *map_host, uint64_t *ticket);
+
+/* *done = 1 once the request has finished (completed, cancelled or failed). */
+int rs_server_poll(rs_server *server, uint64_t ticket, int *done);
+
+/*
+ * Block until the request has finished, then release the ticket. Returns
+ * RS_OK (map written, stats and latency filled), RS_ECANCELED, RS_ENOMEM (its
+ * footprint exceeds the whole pool) or RS_EHIP.
+ */
+int rs_server_wait(rs_server *server, uint64_t ticket, rs_map_stats *stats, double *latency_s);
+
+/* Cancel a waiting or running request; work already on the device is discarded. */
+int rs_server_cancel(rs_server *server, uint64_t ticket);
+
+/* Counters, throughput and latency percentiles of the server so far. */
+int rs_server_get_stats(rs_server *server, rs_server_stats *stats);
+
+/* Stop admitting, drop waiting requests, finish running ones, release everything. */
+void rs_server_destroy(rs_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ Public entry points (loaded lazily so that importing the package, e.g. for
 """
 _API = ("make_map", "ray_pixels", "read_stats", "workspace_bytes", "new_workspace", "to_params",
         "lens_tensors", "profile_enable", "profile_read", "version", "tune", "set_shape", "tune_save",
-        "tune_load")
+        "tune_load", "make_maps", "Batch", "Server")
 
 
 def __getattr__(name):

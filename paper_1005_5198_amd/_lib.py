@@ -54,6 +54,27 @@ class MapStats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class MapRequest(ctypes.Structure):
+    _fields_ = [("params", MapParams), ("lens_xy", ctypes.c_void_p), ("lens_m", ctypes.c_void_p),
+                ("n_lens", ctypes.c_int64), ("map", ctypes.c_void_p)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("slice_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("completed", "canceled", "failed", "steps", "waiting", "active",
+                                               "max_waiting", "hbm_in_use_bytes", "hbm_peak_bytes")] + \
+               [(n, ctypes.c_double) for n in ("interactions", "gpu_busy_s", "maps_per_s", "latency_p50_s",
+                                               "latency_p99_s", "latency_mean_s", "latency_max_s")]
+
+    def as_dict(self) -> dict:
+        return {k: (int(v) if isinstance(v, int) else float(v)) for k, v in
+                ((k, getattr(self, k)) for k, _ in self._fields_)}
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int32), ("n_shapes", ctypes.c_int32),
                 ("rays_per_lane", (ctypes.c_int32 * 2) * 8), ("threads", ctypes.c_int32 * 8),
@@ -83,6 +104,16 @@ def _declare(lib):
         "rs_set_shape": ([INT, ctypes.POINTER(INT)], INT),
         "rs_tune_save": ([ctypes.c_char_p], INT),
         "rs_tune_load": ([ctypes.c_char_p], INT),
+        "rs_batch_workspace_bytes": ([P(MapRequest), ctypes.c_int32], SZ),
+        "rs_make_maps": ([P(MapRequest), ctypes.c_int32, VP, SZ, VP], INT),
+        "rs_batch_read_stats": ([VP, ctypes.c_int32, P(MapStats), VP], INT),
+        "rs_server_create": ([P(ServerCfg), P(VP)], INT),
+        "rs_server_submit": ([VP, P(MapParams), VP, VP, I64, VP, P(ctypes.c_uint64)], INT),
+        "rs_server_poll": ([VP, ctypes.c_uint64, P(INT)], INT),
+        "rs_server_wait": ([VP, ctypes.c_uint64, P(MapStats), P(ctypes.c_double)], INT),
+        "rs_server_cancel": ([VP, ctypes.c_uint64], INT),
+        "rs_server_get_stats": ([VP, P(ServerStats)], INT),
+        "rs_server_destroy": ([VP], None),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -112,4 +143,6 @@ def exported_symbols():
     """Names of the C-ABI functions this binding declares."""
     return ["rs_version", "rs_last_error", "rs_workspace_bytes", "rs_make_map", "rs_ray_pixels",
             "rs_read_stats", "rs_profile_enable", "rs_profile_read", "rs_tune", "rs_set_shape",
-            "rs_tune_save", "rs_tune_load"]
+            "rs_tune_save", "rs_tune_load", "rs_batch_workspace_bytes", "rs_make_maps",
+            "rs_batch_read_stats", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
+            "rs_server_cancel", "rs_server_get_stats", "rs_server_destroy"]

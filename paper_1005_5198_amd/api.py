@@ -167,3 +167,122 @@ def tune_save(path: str) -> None:
 
 def tune_load(path: str) -> None:
     L.check(L.lib().rs_tune_load(path.encode()))
+
+
+class Batch:
+    """Device-resident inputs and outputs of a batch of maps, reusable across launches.
+
+    maps: list of (params dict, lens_xy, lens_m or None). All maps share ``mode``.
+    """
+
+    def __init__(self, maps, mode: str = "mixed", device=None):
+        dev = device or _device()
+        self.mode = mode
+        self.lenses = [lens_tensors(xy, m, dev) for (_, xy, m) in maps]
+        self.params = [p for (p, _, _) in maps]
+        self.outs = [torch.empty((int(p["npy"]), int(p["npx"])), dtype=torch.uint32, device=dev)
+                     for p in self.params]
+        n = len(maps)
+        self.reqs = (L.MapRequest * n)()
+        for k, (p, (xy, m)) in enumerate(zip(self.params, self.lenses)):
+            r = self.reqs[k]
+            r.params = to_params(p, mode)
+            r.lens_xy = _ptr(xy)
+            r.lens_m = _ptr(m)
+            r.n_lens = xy.shape[0]
+            r.map = self.outs[k].data_ptr()
+        nbytes = L.lib().rs_batch_workspace_bytes(self.reqs, n)
+        if nbytes == 0:
+            L.check(L.RS_EINVAL)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    @property
+    def interactions(self) -> int:
+        return sum(int((p["i1"] - p["i0"]) * (p["j1"] - p["j0"])) * xy.shape[0]
+                   for p, (xy, _) in zip(self.params, self.lenses))
+
+    def run(self, stream=None):
+        """Enqueue every map of the batch (asynchronous)."""
+        L.check(L.lib().rs_make_maps(self.reqs, len(self.params), self.workspace.data_ptr(),
+                                     self.workspace.numel(), _stream_handle(stream)))
+        return self.outs
+
+    def stats(self, stream=None):
+        n = len(self.params)
+        st = (L.MapStats * n)()
+        L.check(L.lib().rs_batch_read_stats(self.workspace.data_ptr(), n, st, _stream_handle(stream)))
+        return [s.as_dict() for s in st]
+
+
+def make_maps(maps, mode: str = "mixed", stream=None, return_stats: bool = False):
+    """Build many maps in one persistent launch; returns a list of uint32 [npy, npx] tensors."""
+    b = Batch(maps, mode)
+    outs = b.run(stream)
+    if return_stats:
+        return outs, b.stats(stream)
+    return outs
+
+
+class Server:
+    """The request loop (continuous batching). Inputs are host arrays; results come back as numpy maps."""
+
+    def __init__(self, hbm_budget_bytes: int = 1 << 30, max_inflight: int = 16, mode: str = "mixed",
+                 slice_ms: float = 20.0):
+        _device()
+        cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms))
+        h = ctypes.c_void_p()
+        L.check(L.lib().rs_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}   # ticket -> (host map, keep-alive arrays)
+        self.mode = mode
+
+    def submit(self, params: dict, lens_xy, lens_m=None) -> int:
+        xy = np.ascontiguousarray(np.asarray(lens_xy, dtype=np.float64).reshape(-1, 2))
+        m = None if lens_m is None else np.ascontiguousarray(np.asarray(lens_m, dtype=np.float64).reshape(-1))
+        out = np.zeros((int(params["npy"]), int(params["npx"])), dtype=np.uint32)
+        c = to_params(params, self.mode)
+        t = ctypes.c_uint64()
+        L.check(L.lib().rs_server_submit(self._h, ctypes.byref(c), xy.ctypes.data if xy.shape[0] else None,
+                                         None if m is None else m.ctypes.data, xy.shape[0], out.ctypes.data,
+                                         ctypes.byref(t)))
+        self._pending[t.value] = out
+        return t.value
+
+    def done(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        L.check(L.lib().rs_server_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        """(map numpy uint32, stats dict, latency seconds); raises RayshootError if cancelled or failed."""
+        st = L.MapStats()
+        lat = ctypes.c_double()
+        rc = L.lib().rs_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(lat))
+        out = self._pending.pop(ticket, None)
+        L.check(rc)
+        return out, st.as_dict(), lat.value
+
+    def cancel(self, ticket: int) -> None:
+        L.check(L.lib().rs_server_cancel(self._h, ticket))
+
+    def stats(self) -> dict:
+        st = L.ServerStats()
+        L.check(L.lib().rs_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            L.lib().rs_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

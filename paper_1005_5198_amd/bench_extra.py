@@ -1,0 +1,123 @@
+"""Batched and served measurements for bench.py.
+
+batched(): the 64-map batch (config 3 distribution) in one persistent launch
+sequence vs the same maps one at a time through rs_make_map; every batched map
+is compared with its one-at-a-time result (bit-identical).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import workloads as w
+
+
+def batched(rs, n_maps: int = 64, mode: str = "mixed", repeats: int = 1, check: bool = True) -> dict:
+    specs = w.config3(n_maps)
+    items = [(s.params, s.lens_xy, s.lens_m) for s in specs]
+    b = rs.Batch(items, mode=mode)
+    inter = b.interactions
+    b.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(repeats):
+        outs = b.run()
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t) / repeats
+    batch_maps = [o.cpu().numpy() for o in outs]
+    # one at a time, same inputs already on the device
+    plain_out = [torch.empty_like(o) for o in outs]
+    # one workspace, sized for the largest map, reused by the sequential launches on one stream
+    ws = torch.empty(max(rs.workspace_bytes(p, xy.shape[0], mode) for p, (xy, _) in zip(b.params, b.lenses)),
+                     dtype=torch.uint8, device="cuda")
+    for p, (xy, m), o in zip(b.params, b.lenses, plain_out):
+        rs.make_map(p, xy, m, mode=mode, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(repeats):
+        for p, (xy, m), o in zip(b.params, b.lenses, plain_out):
+            rs.make_map(p, xy, m, mode=mode, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t) / repeats
+    identical = None
+    if check:
+        identical = all(np.array_equal(a, o.cpu().numpy()) for a, o in zip(batch_maps, plain_out))
+    return {"workload": f"config3: {n_maps} maps (sigma*~U[0.2,0.8], s~U[0,0.5], gamma~U[0,0.4], "
+                        f"256^2-1024^2 px, 200 rays/px), {mode} mode",
+            "maps": n_maps, "interactions": inter,
+            "batched_maps_per_s": n_maps / dt_batch, "batched_value": inter / dt_batch,
+            "plain_maps_per_s": n_maps / dt_plain, "plain_value": inter / dt_plain,
+            "speedup": dt_plain / dt_batch, "batched_s": dt_batch, "plain_s": dt_plain,
+            "identical_to_plain": identical}
+
+
+def _percentiles(lat):
+    a = np.sort(np.asarray(lat))
+    def rank(p):
+        k = int(np.ceil(p / 100.0 * len(a)))
+        return float(a[min(max(k, 1), len(a)) - 1])
+    return rank(50), rank(99)
+
+
+def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed: int = 4,
+           budget_bytes: int = 2 << 30, max_inflight: int = 16, slice_ms: float = 20.0) -> dict:
+    """Poisson arrivals of config-3-distributed requests (each with its own lens set):
+    the request loop vs the same arrivals served one at a time by plain rs_make_map calls."""
+    import threading
+
+    _, specs = w.config4_arrivals(n_requests, 1.0, seed=seed)
+    # plain service rate of this request mix (one at a time, inputs from the host, map back to the host)
+    def plain_one(s):
+        out = rs.make_map(s.params, s.lens_xy, s.lens_m, mode=mode)
+        return out.cpu().numpy()
+    plain_one(specs[0])
+    t = time.perf_counter()
+    for s in specs[: min(8, n_requests)]:
+        plain_one(s)
+    plain_rate = min(8, n_requests) / (time.perf_counter() - t)
+    rate = rho * plain_rate
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+
+    # one at a time (FIFO): latency = completion - arrival
+    lat_plain = []
+    t0 = time.perf_counter()
+    for s, a in zip(specs, arrivals):
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+        plain_one(s)
+        lat_plain.append(time.perf_counter() - t0 - a)
+    span_plain = time.perf_counter() - t0
+
+    # the request loop
+    tickets = [None] * n_requests
+    with rs.Server(hbm_budget_bytes=budget_bytes, max_inflight=max_inflight, mode=mode, slice_ms=slice_ms) as srv:
+        t0 = time.perf_counter()
+
+        def feed():
+            for k, (s, a) in enumerate(zip(specs, arrivals)):
+                now = time.perf_counter() - t0
+                if now < a:
+                    time.sleep(a - now)
+                tickets[k] = srv.submit(s.params, s.lens_xy, s.lens_m)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        served_maps = [srv.wait(tk)[0] for tk in tickets]
+        span_served = time.perf_counter() - t0
+        st = srv.stats()
+    identical = all(np.array_equal(m, plain_one(s)) for m, s in zip(served_maps[:8], specs[:8]))
+    p50p, p99p = _percentiles(lat_plain)
+    inter = sum(s.interactions for s in specs)
+    return {"workload": f"config4: {n_requests} Poisson requests at rho={rho} of the one-at-a-time rate "
+                        f"({rate:.2f}/s), config-3 distribution, {mode} mode",
+            "requests": n_requests, "arrival_rate_per_s": rate, "interactions": inter,
+            "served_maps_per_s": st["maps_per_s"], "served_p50_s": st["latency_p50_s"],
+            "served_p99_s": st["latency_p99_s"], "served_span_s": span_served, "served_steps": st["steps"],
+            "served_max_waiting": st["max_waiting"], "served_hbm_peak_bytes": st["hbm_peak_bytes"],
+            "plain_maps_per_s": n_requests / span_plain, "plain_p50_s": p50p, "plain_p99_s": p99p,
+            "plain_span_s": span_plain, "identical_first8": identical}

@@ -25,7 +25,7 @@ ARCH = os.environ.get("RAYSHOOT_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-shared", "-std=c++17",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
+         "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable", "-Wno-pass-failed",
          f"-I{INCLUDE}", f"-I{CSRC}", "-lpthread"]
 
 

@@ -1,0 +1,154 @@
+// Host side of the batched path: validate the requests, order the work list
+// (most expensive maps first, so the tail of the persistent launch is made of
+// cheap tiles), upload the descriptors into the workspace, and enqueue
+// fill -> persistent deflection -> batched FP64 re-check.
+#include "rs_internal.h"
+#include "rayshoot.h"
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+namespace rs {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate(const rs_map_params *p, int64_t n_lens);
+int choose_shape(int mode, bool unit, int64_t n_lens);
+void profile_begin(hipStream_t stream, void **token);
+int profile_end(hipStream_t stream, void *token, double interactions);
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+// Workspace bytes: globals, descriptors, counters, and two bitmaps per map.
+static size_t batch_bytes(const rs_map_request *reqs, int32_t n) {
+    size_t off = batch_bitmaps_offset(n);
+    for (int32_t k = 0; k < n; ++k) off += 2 * 4 * (size_t)bitmap_words_of(reqs[k].params);
+    return off;
+}
+
+size_t rs_batch_workspace_bytes(const rs_map_request *reqs, int32_t n) {
+    if (!reqs || n < 1 || n > 65536) return 0;
+    for (int32_t k = 0; k < n; ++k)
+        if (validate(&reqs[k].params, reqs[k].n_lens) != RS_OK) return 0;
+    return batch_bytes(reqs, n);
+}
+
+int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!reqs || n < 1 || n > 65536) return fail(RS_EINVAL, "need 1..65536 requests");
+    if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
+    const int mode = reqs[0].params.mode;
+    for (int32_t k = 0; k < n; ++k) {
+        const rs_map_request &r = reqs[k];
+        int rc = validate(&r.params, r.n_lens);
+        if (rc) return fail(rc, "request %d: %s", k, rs_last_error());
+        if (r.params.mode != mode) return fail(RS_EINVAL, "request %d: every request of a batch needs the same mode", k);
+        if (!r.map) return fail(RS_EINVAL, "request %d: map is NULL", k);
+        if (r.n_lens > 0 && !r.lens_xy) return fail(RS_EINVAL, "request %d: lens_xy is NULL", k);
+        if ((reinterpret_cast<uintptr_t>(r.lens_xy) | reinterpret_cast<uintptr_t>(r.lens_m)) & 7)
+            return fail(RS_EINVAL, "request %d: lens arrays must be 8-byte aligned", k);
+        const double rays = (double)(r.params.i1 - r.params.i0) * (double)(r.params.j1 - r.params.j0);
+        if (rays >= 4294967296.0) return fail(RS_EINVAL, "request %d: window holds 2^32 rays or more", k);
+    }
+    const size_t need = batch_bytes(reqs, n);
+    if (workspace_bytes < need) return fail(RS_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return reqs[x].n_lens > reqs[y].n_lens; });
+
+    char *ws = static_cast<char *>(workspace);
+    auto *counters = reinterpret_cast<unsigned long long *>(ws + batch_counters_offset(n));
+    std::vector<uint32_t *> bitmaps(n);
+    {
+        size_t off = batch_bitmaps_offset(n);
+        for (int32_t k = 0; k < n; ++k) {
+            bitmaps[k] = reinterpret_cast<uint32_t *>(ws + off);
+            off += 2 * 4 * (size_t)bitmap_words_of(reqs[k].params);
+        }
+    }
+    std::vector<BatchMap> maps(n);
+    int64_t tiles = 0, words = 0;
+    double interactions = 0.0;
+    bool unit = true;
+    for (int32_t w = 0; w < n; ++w) {
+        const int32_t k = order[w];
+        const rs_map_request &r = reqs[k];
+        BatchMap &m = maps[w];
+        m = BatchMap{};
+        m.p = r.params;
+        m.lens_xy = r.lens_xy;
+        m.lens_m = r.lens_m;
+        m.n_lens = r.n_lens;
+        m.map = r.map;
+        m.counters = counters + (size_t)k * N_COUNTERS;
+        const int64_t W = r.params.i1 - r.params.i0, H = r.params.j1 - r.params.j0;
+        m.n_tiles = (W > 0 && H > 0) ? ((W + PATCH_X - 1) / PATCH_X) * ((H + PATCH_Y - 1) / PATCH_Y) : 0;
+        m.tile_begin = tiles;
+        m.n_words = bitmap_words_of(r.params);
+        m.word_begin = words;
+        m.flag_bits = bitmaps[k];
+        m.unres_bits = bitmaps[k] + m.n_words;
+        m.request = k;
+        m.accumulate = (r.params.flags & RS_ACCUMULATE) ? 1 : 0;
+        if (r.lens_m != nullptr) unit = false;
+        tiles += m.n_tiles;
+        words += m.n_words;
+        interactions += (double)W * (double)H * (double)r.n_lens;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(ws + batch_maps_offset(), maps.data(), sizeof(BatchMap) * (size_t)n,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "uploading batch descriptors");
+
+    BatchArgs b{};
+    b.maps = reinterpret_cast<const BatchMap *>(ws + batch_maps_offset());
+    b.n_maps = n;
+    b.mode = mode;
+    b.unit_masses = unit ? 1 : 0;
+    b.total_tiles = tiles;
+    b.total_words = words;
+    b.tile_counter = reinterpret_cast<unsigned long long *>(ws);
+    b.unresolved = reinterpret_cast<unsigned int *>(ws + 8);
+
+    e = launch_batch_fill(b, workspace, n, s);
+    if (e != hipSuccess) return hip_fail(e, "batch fill kernel");
+    const rs_map_request &heavy = reqs[order[0]];
+    const int shape = choose_shape(mode, heavy.lens_m == nullptr, heavy.n_lens);
+    void *tok = nullptr;
+    profile_begin(s, &tok);
+    e = launch_shoot_batch(b, shape, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "batched deflection kernel");
+    int rc = profile_end(s, tok, interactions);
+    if (rc) return rc;
+    if (mode == RS_MIXED) {
+        e = launch_recheck_batch(b, s);
+        if (e != hipSuccess) return hip_fail(e, "batched re-check kernels");
+    }
+    return RS_OK;
+}
+
+int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_host, void *stream) {
+    if (!workspace || !stats_host || n < 1 || n > 65536) return fail(RS_EINVAL, "bad arguments");
+    std::vector<unsigned long long> c((size_t)n * N_COUNTERS);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(c.data(), static_cast<const char *>(workspace) + batch_counters_offset(n),
+                                  c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading batch stats");
+    for (int32_t k = 0; k < n; ++k) {
+        const unsigned long long *q = &c[(size_t)k * N_COUNTERS];
+        stats_host[k].rays_in_map = q[C_IN];
+        stats_host[k].rays_out = q[C_OUT];
+        stats_host[k].rays_singular = q[C_SING];
+        stats_host[k].rays_rechecked = q[C_RECHECK];
+        stats_host[k].rays_shot = q[C_IN] + q[C_OUT] + q[C_SING];
+    }
+    return RS_OK;
+}
+
+}  // extern "C"

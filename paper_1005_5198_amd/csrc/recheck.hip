@@ -1,96 +1,26 @@
 // FP64 re-evaluation of rays whose FP32 source position is within its error
-// bound of a pixel edge.
-//
-// The arithmetic is the plain definition, operation for operation:
-//   - ray position, Section 3.1 regular grid, cell-centred:
-//       x1 = sx0 + ((double)i + 0.5) * (sw / nx)
-//   - Section 2, Eq. (sigma): a1 = sum_k (m_k / r2) * d1 in lens order k = 0..N-1,
-//     d1 = x1 - X_k, r2 = d1*d1 + d2*d2, sequential, no fused multiply-add
-//     (the library is compiled with -ffp-contract=off), IEEE division; a ray
-//     with r2 == 0 is singular;
-//   - y1 = ((1 - gamma) - sigma_c) * x1 - a1, u = (y1 - tx0) / (tw / npx);
-//   - pixel floor(u), floor(v) if 0 <= u < npx and 0 <= v < npy, else out.
-// Because every operation is an IEEE-754 binary64 operation in the same
-// order, the result of a re-checked ray is the definition's result bit for bit.
+// bound of a pixel edge (the arithmetic lives in recheck_ray.h).
 //
 // Two stages keep the exact evaluation rare:
-//   stage A (recheck_fast_kernel): FP64 with fused multiply-adds and a
-//     Newton-refined v_rcp_f64, plus a running sum S = sum (|d1|+|d2|) m/r^2
-//     that bounds the error of both this evaluation and the definition's own
-//     FP64 rounding by 2 [(N + 10) 2^-53 S + 2^-50 (|c1 x1| + |a1| + |tx0|)]
-//     (in source-plane units). A ray whose position is farther than that from
-//     every pixel edge is decided here, identically to the definition.
-//   stage B (recheck_exact_wave_kernel): the remaining rays (marked in the
-//     queue) are evaluated with the definition's exact operation sequence, one
-//     wave per ray: the 64 lanes compute the per-lens terms (m/r^2) d1 and
-//     (m/r^2) d2 for 64 lenses at a time, and the lens-order sum then adds
-//     them one by one, so every rounding step is the definition's.
-// Stage A and the exact-only path run one thread per queued ray; every lane of
-// a wave walks the lens list in the same order, so lens loads are wave-uniform.
-#include "rs_internal.h"
+//   stage A (fast_ray): FP64 with fused multiply-adds and a bound that also
+//     covers the definition's own FP64 rounding; it decides almost every
+//     queued ray identically to the definition and marks the rest;
+//   stage B (exact_ray_wave): the marked rays, one wave per ray, with the
+//     definition's exact operation sequence.
+// RS_EXACT_RECHECK runs the exact sequence for every queued ray instead (one
+// thread per ray).
+//
+// Single map: the queue holds uint32 chunk-relative ray indices.
+// Batch: the deflection kernel sets one bit per flagged ray in each map's
+// bitmap; a persistent scan compacts the set bits per wave and the map's
+// descriptor supplies its parameters.
+#include "recheck_ray.h"
 
 namespace rs {
 namespace {
 
-constexpr uint32_t UNRESOLVED = 0x80000000u;  // queue-entry mark set by stage A
-
-template <bool UNIT, bool PIX>
-__global__ __launch_bounds__(256) void recheck_kernel(const RecheckArgs a) {
-    const uint32_t n = *a.qcount;
-    const int64_t W = a.i1 - a.i0;
-    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
-    const double spx = a.sw / (double)a.nx;
-    const double spy = a.sh / (double)a.ny;
-    const double c1 = (1.0 - a.gamma) - a.sigma_c;
-    const double c2 = (1.0 + a.gamma) - a.sigma_c;
-    const double pixw = a.tw / (double)a.npx;
-    const double pixh = a.th / (double)a.npy;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
-        const uint32_t q = a.queue[idx];
-        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
-        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
-        const double x1 = a.sx0 + ((double)i + 0.5) * spx;
-        const double x2 = a.sy0 + ((double)j + 0.5) * spy;
-        double a1 = 0.0, a2 = 0.0;
-        bool singular = false;
-        for (int64_t k = 0; k < a.n_lens; ++k) {
-            const double d1 = x1 - a.lens_xy[2 * k];
-            const double d2 = x2 - a.lens_xy[2 * k + 1];
-            const double r2 = d1 * d1 + d2 * d2;
-            if (r2 == 0.0) {
-                singular = true;
-                break;
-            }
-            const double m = UNIT ? 1.0 : a.lens_m[k];
-            const double f = m / r2;
-            a1 += f * d1;
-            a2 += f * d2;
-        }
-        int code;
-        if (singular) {
-            code = -2;
-            ++n_sing;
-        } else {
-            const double y1 = c1 * x1 - a1;
-            const double y2 = c2 * x2 - a2;
-            const double u = (y1 - a.tx0) / pixw;
-            const double v = (y2 - a.ty0) / pixh;
-            if (isfinite(u) && isfinite(v) && u >= 0.0 && u < (double)a.npx && v >= 0.0 &&
-                v < (double)a.npy) {
-                code = (int)((int64_t)floor(v) * a.npx + (int64_t)floor(u));
-                ++n_in;
-            } else {
-                code = -1;
-                ++n_out;
-            }
-        }
-        if (PIX) {
-            a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-        } else if (code >= 0) {
-            atomicAdd(a.map + code, 1u);
-        }
-    }
+__device__ inline void count_wave(unsigned long long *counters, unsigned long long n_in,
+                                  unsigned long long n_out, unsigned long long n_sing) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         n_in += __shfl_xor(n_in, off);
@@ -98,35 +28,73 @@ __global__ __launch_bounds__(256) void recheck_kernel(const RecheckArgs a) {
         n_sing += __shfl_xor(n_sing, off);
     }
     if (__lane_id() == 0) {
-        if (n_in) atomicAdd(a.counters + C_IN, n_in);
-        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
-        if (n_sing) atomicAdd(a.counters + C_SING, n_sing);
+        if (n_in) atomicAdd(counters + C_IN, n_in);
+        if (n_out) atomicAdd(counters + C_OUT, n_out);
+        if (n_sing) atomicAdd(counters + C_SING, n_sing);
     }
+}
+
+__device__ inline void tally(int code, unsigned long long &n_in, unsigned long long &n_out,
+                             unsigned long long &n_sing) {
+    if (code >= 0) ++n_in;
+    else if (code == CODE_OUT) ++n_out;
+    else ++n_sing;
+}
+
+__device__ inline void place(const RecheckArgs &a, int64_t i, int64_t j, int code) {
+    if (a.pix_out) a.pix_out[(j - a.j0) * (a.i1 - a.i0) + (i - a.i0)] = code;
+    else if (code >= 0) atomicAdd(a.map + code, 1u);
+}
+
+// ----------------------------- single map ---------------------------------
+
+template <bool UNIT>
+__global__ __launch_bounds__(256) void recheck_exact_kernel(const RecheckArgs a) {
+    const uint32_t n = *a.qcount;
+    const int64_t W = a.i1 - a.i0;
+    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        const uint32_t q = a.queue[idx];
+        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
+        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
+        const int code = exact_ray_thread<UNIT>(a, i, j);
+        tally(code, n_in, n_out, n_sing);
+        place(a, i, j, code);
+    }
+    count_wave(a.counters, n_in, n_out, n_sing);
     if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+template <bool UNIT>
+__global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) {
+    const uint32_t n = *a.qcount;
+    const int64_t W = a.i1 - a.i0;
+    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        const uint32_t q = a.queue[idx];
+        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
+        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
+        int code;
+        if (fast_ray<UNIT>(a, i, j, code)) {
+            tally(code, n_in, n_out, n_sing);
+            place(a, i, j, code);
+        } else {
+            a.queue[idx] = q | UNRESOLVED;
+        }
+    }
+    count_wave(a.counters, n_in, n_out, n_sing);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
 }
 
-// Stage B: rays marked UNRESOLVED by stage A, one wave per ray.
-template <bool UNIT, bool PIX>
+template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_exact_wave_kernel(const RecheckArgs a) {
     const uint32_t n = *a.qcount;
     const int64_t W = a.i1 - a.i0;
     const int lane = __lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
-    const double spx = a.sw / (double)a.nx;
-    const double spy = a.sh / (double)a.ny;
-    const double c1 = (1.0 - a.gamma) - a.sigma_c;
-    const double c2 = (1.0 + a.gamma) - a.sigma_c;
-    const double pixw = a.tw / (double)a.npx;
-    const double pixh = a.th / (double)a.npy;
-    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
     for (uint32_t base = wave_id * 64u; base < n; base += n_waves * 64u) {
         const uint32_t idx = base + (uint32_t)lane;
         const uint32_t q_lane = idx < n ? a.queue[idx] : 0u;
@@ -137,144 +105,136 @@ __global__ __launch_bounds__(256) void recheck_exact_wave_kernel(const RecheckAr
             const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)q_lane, src) & ~UNRESOLVED;
             const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
             const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
-            const double x1 = a.sx0 + ((double)i + 0.5) * spx;
-            const double x2 = a.sy0 + ((double)j + 0.5) * spy;
-            double a1 = 0.0, a2 = 0.0;
-            bool singular = false;
-            for (int64_t k0 = 0; k0 < a.n_lens; k0 += 64) {
-                const int64_t k = k0 + lane;
-                double t1 = 0.0, t2 = 0.0;
-                bool zero = false;
-                if (k < a.n_lens) {
-                    const double d1 = x1 - a.lens_xy[2 * k];
-                    const double d2 = x2 - a.lens_xy[2 * k + 1];
-                    const double r2 = d1 * d1 + d2 * d2;
-                    zero = (r2 == 0.0);
-                    const double m = UNIT ? 1.0 : a.lens_m[k];
-                    const double f = m / r2;
-                    t1 = f * d1;
-                    t2 = f * d2;
-                }
-                if (__ballot(zero)) {
-                    singular = true;
-                    break;
-                }
-                const int cnt = (a.n_lens - k0) < 64 ? (int)(a.n_lens - k0) : 64;
-                for (int l = 0; l < cnt; ++l) {
-                    a1 += readlane_f64(t1, l);
-                    a2 += readlane_f64(t2, l);
-                }
-            }
-            int code;
-            if (singular) {
-                code = -2;
-                ++n_sing;
-            } else {
-                const double y1 = c1 * x1 - a1;
-                const double y2 = c2 * x2 - a2;
-                const double u = (y1 - a.tx0) / pixw;
-                const double v = (y2 - a.ty0) / pixh;
-                if (isfinite(u) && isfinite(v) && u >= 0.0 && u < (double)a.npx && v >= 0.0 &&
-                    v < (double)a.npy) {
-                    code = (int)((int64_t)floor(v) * a.npx + (int64_t)floor(u));
-                    ++n_in;
-                } else {
-                    code = -1;
-                    ++n_out;
-                }
-            }
-            if (lane == 0) {
-                if (PIX) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-                else if (code >= 0) atomicAdd(a.map + code, 1u);
-            }
+            const int code = exact_ray_wave<UNIT>(a, i, j);
+            if (lane == 0) emit_ray(a, i, j, code);
         }
-    }
-    if (lane == 0) {
-        if (n_in) atomicAdd(a.counters + C_IN, n_in);
-        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
-        if (n_sing) atomicAdd(a.counters + C_SING, n_sing);
     }
 }
 
-// Stage A. Decides every queued ray whose FP64 position is provably on the
-// same side of every pixel edge as the definition's; marks the others.
-template <bool UNIT, bool PIX>
-__global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) {
-    const uint32_t n = *a.qcount;
-    const int64_t W = a.i1 - a.i0;
-    unsigned long long n_in = 0, n_out = 0;
-    const double spx = a.sw / (double)a.nx;
-    const double spy = a.sh / (double)a.ny;
-    const double c1 = (1.0 - a.gamma) - a.sigma_c;
-    const double c2 = (1.0 + a.gamma) - a.sigma_c;
-    const double inv_pixw = (double)a.npx / a.tw;
-    const double inv_pixh = (double)a.npy / a.th;
-    const double U64 = 1.1102230246251565e-16;  // 2^-53
-    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
-        const uint32_t q = a.queue[idx];
-        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
-        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
-        const double x1 = a.sx0 + ((double)i + 0.5) * spx;
-        const double x2 = a.sy0 + ((double)j + 0.5) * spy;
-        double a1 = 0.0, a2 = 0.0, S = 0.0;
-        bool tiny = false;
-#pragma unroll 4
-        for (int64_t k = 0; k < a.n_lens; ++k) {
-            const double d1 = x1 - a.lens_xy[2 * k];
-            const double d2 = x2 - a.lens_xy[2 * k + 1];
-            const double r2 = __builtin_fma(d1, d1, d2 * d2);
-            tiny |= !(r2 > 1e-200);
-            double rc = __builtin_amdgcn_rcp(r2);
-            double e = __builtin_fma(-r2, rc, 1.0);
-            rc = __builtin_fma(rc, e, rc);
-            e = __builtin_fma(-r2, rc, 1.0);
-            rc = __builtin_fma(rc, e, rc);
-            if (!UNIT) rc = rc * a.lens_m[k];
-            a1 = __builtin_fma(d1, rc, a1);
-            a2 = __builtin_fma(d2, rc, a2);
-            S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
+// ------------------------------- batch -------------------------------------
+
+__device__ inline RecheckArgs batch_recheck_args(const BatchMap &m) {
+    return recheck_args_of(m.p, m.lens_xy, m.lens_m, m.n_lens, m.map, m.counters);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    // LDS operations of one wave execute in order; keep the compiler from moving
+    // them across this point.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Stage A for the entries held one per lane (valid lanes only): lanes are
+// grouped by map, and each group runs with its map's parameters in scalar
+// registers. Rays are decided, or marked for the exact stage.
+__device__ inline void batch_stage_a(const BatchArgs &b, QueueEntry e, bool valid) {
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t mi = (uint32_t)__builtin_amdgcn_readlane((int)e.map, leader);
+        const bool mine = valid && e.map == mi;
+        pending &= ~__ballot(mine);
+        const BatchMap &m = b.maps[mi];
+        const RecheckArgs a = make_uniform(batch_recheck_args(m));
+        uint32_t *const unres = make_uniform(m.unres_bits);
+        int code = CODE_OUT;
+        bool ok = false;
+        if (mine) {
+            const int64_t W = a.i1 - a.i0;
+            const int64_t i = a.i0 + (int64_t)(e.ray % (uint64_t)W);
+            const int64_t j = a.j0 + (int64_t)(e.ray / (uint64_t)W);
+            ok = a.lens_m == nullptr ? fast_ray<true>(a, i, j, code) : fast_ray<false>(a, i, j, code);
+            if (ok) {
+                if (code >= 0) atomicAdd(a.map + code, 1u);
+            } else {
+                atomicOr(unres + (e.ray >> 5), 1u << (e.ray & 31u));
+            }
         }
-        const double y1 = c1 * x1 - a1;
-        const double y2 = c2 * x2 - a2;
-        const double u = (y1 - a.tx0) * inv_pixw;
-        const double v = (y2 - a.ty0) * inv_pixh;
-        const double Mu = 2.002 * (kN * S + 8.0 * U64 * (fabs(c1 * x1) + fabs(a1) + fabs(a.tx0))) * inv_pixw;
-        const double Mv = 2.002 * (kN * S + 8.0 * U64 * (fabs(c2 * x2) + fabs(a2) + fabs(a.ty0))) * inv_pixh;
-        const double fu = floor(u), fv = floor(v);
-        const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
-        const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
-        const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
-        const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
-        const bool sane = !tiny && isfinite(S) && isfinite(Mu) && isfinite(Mv);
-        int code;
-        if (sane && ok_u && ok_v) {
-            code = (int)((int64_t)fv * a.npx + (int64_t)fu);
-            ++n_in;
-        } else if (sane && (out_u || out_v)) {
-            code = -1;
-            ++n_out;
+        // one counter update per group (stage A never yields a singular ray)
+        const unsigned n_in = (unsigned)__builtin_popcountll(__ballot(mine && ok && code >= 0));
+        const unsigned n_out = (unsigned)__builtin_popcountll(__ballot(mine && ok && code < 0));
+        const bool any_unres = __ballot(mine && !ok) != 0;
+        if (__lane_id() == leader) {
+            if (n_in) atomicAdd(a.counters + C_IN, (unsigned long long)n_in);
+            if (n_out) atomicAdd(a.counters + C_OUT, (unsigned long long)n_out);
+            if (any_unres) atomicOr(b.unresolved, 1u);
+        }
+    }
+}
+
+// Exact stage for up to 64 entries held one per lane: one wave per ray.
+__device__ inline void batch_stage_b(const BatchArgs &b, QueueEntry e, int n_valid) {
+    const int lane = __lane_id();
+    for (int s = 0; s < n_valid; ++s) {
+        const uint32_t mi = (uint32_t)__builtin_amdgcn_readlane((int)e.map, s);
+        const uint32_t ray = (uint32_t)__builtin_amdgcn_readlane((int)e.ray, s);
+        const BatchMap &m = b.maps[mi];
+        const RecheckArgs a = make_uniform(batch_recheck_args(m));
+        const int64_t W = a.i1 - a.i0;
+        const int64_t i = a.i0 + (int64_t)(ray % (uint64_t)W);
+        const int64_t j = a.j0 + (int64_t)(ray / (uint64_t)W);
+        const int code = a.lens_m == nullptr ? exact_ray_wave<true>(a, i, j) : exact_ray_wave<false>(a, i, j);
+        if (lane == 0) emit_ray(a, i, j, code);
+    }
+}
+
+// Persistent scan of the batch's bitmaps (STAGE 0: flag bits -> stage A;
+// STAGE 1: unresolved bits -> exact stage). Wave k takes the 64-word blocks
+// k, k + n_waves, k + 2 n_waves, ... of the batch's word space (interleaved, so
+// every wave sees a mix of all maps and no atomics are needed), compacts their
+// set bits into its own ring buffer in LDS, and evaluates them 64 at a time,
+// one per lane. A wave leaves when its blocks are done and its buffer is empty.
+template <int STAGE>
+__global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs b) {
+    if (STAGE == 1 && *b.unresolved == 0u) return;
+    constexpr int RING = 128;
+    __shared__ QueueEntry ring_all[4][RING];
+    const int lane = __lane_id();
+    QueueEntry *ring = ring_all[threadIdx.x >> 6];
+    const uint64_t below = (1ull << lane) - 1ull;
+    int head = 0, tail = 0;  // wave-uniform; tail - head < 64 between evaluations
+    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t fetch = wave_id * BITMAP_WORD_ALIGN; fetch < b.total_words; fetch += n_waves * BITMAP_WORD_ALIGN) {
+        int lo = 0, hi = b.n_maps - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.maps[mid].word_begin <= fetch) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchMap &m = b.maps[lo];
+        const int64_t w = fetch - m.word_begin + lane;
+        uint32_t bits = (STAGE == 0 ? m.flag_bits : m.unres_bits)[w];
+        for (;;) {
+            const uint64_t hm = __ballot(bits != 0u);
+            if (!hm) break;
+            if (bits) {
+                const int bit = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const int pos = (tail + __builtin_popcountll(hm & below)) % RING;
+                ring[pos] = QueueEntry{(uint32_t)lo, (uint32_t)(w * 32 + bit)};
+            }
+            tail += __builtin_popcountll(hm);
+            wave_sync();
+            if (tail - head >= 64) {
+                const QueueEntry e = ring[(head + lane) % RING];
+                head += 64;
+                wave_sync();
+                if (STAGE == 0) batch_stage_a(b, e, true);
+                else batch_stage_b(b, e, 64);
+            }
+        }
+    }
+    const int left = tail - head;
+    if (left > 0) {
+        QueueEntry e{0u, 0u};
+        if (lane < left) e = ring[(head + lane) % RING];
+        if (STAGE == 0) {
+            batch_stage_a(b, e, lane < left);
         } else {
-            a.queue[idx] = q | UNRESOLVED;
-            continue;
-        }
-        if (PIX) {
-            a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-        } else if (code >= 0) {
-            atomicAdd(a.map + code, 1u);
+            batch_stage_b(b, e, left);
         }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        n_in += __shfl_xor(n_in, off);
-        n_out += __shfl_xor(n_out, off);
-    }
-    if (__lane_id() == 0) {
-        if (n_in) atomicAdd(a.counters + C_IN, n_in);
-        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
 }
 
 }  // namespace
@@ -283,26 +243,26 @@ hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_onl
     int64_t blocks = (max_rays + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
-    const bool unit = a.lens_m == nullptr;
-    const bool pix = a.pix_out != nullptr;
     const dim3 grid((unsigned)blocks), block(256);
-#define RS_PAIR(U, P)                                                                        \
-    do {                                                                                     \
-        if (exact_only) {                                                                    \
-            hipLaunchKernelGGL((recheck_kernel<U, P>), grid, block, 0, stream, a);           \
-        } else {                                                                             \
-            hipLaunchKernelGGL((recheck_fast_kernel<U, P>), grid, block, 0, stream, a);      \
-            hipLaunchKernelGGL((recheck_exact_wave_kernel<U, P>), grid, block, 0, stream, a); \
-        }                                                                                    \
-    } while (0)
-    if (unit) {
-        if (pix) RS_PAIR(true, true);
-        else RS_PAIR(true, false);
+    const bool unit = a.lens_m == nullptr;
+    if (exact_only) {
+        if (unit) hipLaunchKernelGGL(recheck_exact_kernel<true>, grid, block, 0, stream, a);
+        else hipLaunchKernelGGL(recheck_exact_kernel<false>, grid, block, 0, stream, a);
+    } else if (unit) {
+        hipLaunchKernelGGL(recheck_fast_kernel<true>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL(recheck_exact_wave_kernel<true>, grid, block, 0, stream, a);
     } else {
-        if (pix) RS_PAIR(false, true);
-        else RS_PAIR(false, false);
+        hipLaunchKernelGGL(recheck_fast_kernel<false>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL(recheck_exact_wave_kernel<false>, grid, block, 0, stream, a);
     }
-#undef RS_PAIR
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck_batch(const BatchArgs &b, hipStream_t stream) {
+    if (b.total_words <= 0) return hipSuccess;
+    const dim3 grid(2048), block(256);
+    hipLaunchKernelGGL(recheck_scan_batch_kernel<0>, grid, block, 0, stream, b);
+    hipLaunchKernelGGL(recheck_scan_batch_kernel<1>, grid, block, 0, stream, b);
     return hipGetLastError();
 }
 

@@ -1,0 +1,185 @@
+// Per-ray FP64 re-evaluation, shared by the re-check kernels (single map and
+// batch) and by the deflection kernel's in-place fallback when a batch queue
+// is full.
+//
+// exact_ray_*: the plain definition, operation for operation —
+//   ray position (Section 3.1 regular grid, cell-centred):
+//       x1 = sx0 + ((double)i + 0.5) * (sw / nx)
+//   Section 2, Eq. (sigma): a1 = sum_k (m_k / r2) * d1 in lens order,
+//       d1 = x1 - X_k, r2 = d1*d1 + d2*d2; a ray with r2 == 0 is singular;
+//   y1 = ((1 - gamma) - sigma_c) * x1 - a1, u = (y1 - tx0) / (tw / npx);
+//   pixel floor(u), floor(v) if 0 <= u < npx and 0 <= v < npy, else out.
+// Every operation is one IEEE-754 binary64 operation (no contraction: the
+// library is compiled with -ffp-contract=off), so the result is the
+// definition's, bit for bit.
+//
+// fast_ray: FP64 with fused multiply-adds and a Newton-refined v_rcp_f64,
+// plus S = sum (|d1|+|d2|) |m|/r2. Its deviation from the exact real value,
+// and the definition's own, are each at most (N+10) 2^-53 S + 8 2^-53
+// (|c1 x1| + |a1| + |tx0|) in source units; a ray farther than twice that
+// from every pixel edge is decided identically to the definition.
+#pragma once
+
+#include "rs_internal.h"
+
+namespace rs {
+
+constexpr uint32_t UNRESOLVED = 0x80000000u;  // queue mark: stage A could not place the ray
+
+// A copy of a wave-uniform struct whose every 32-bit word goes through
+// readfirstlane, so the compiler keeps it in scalar registers.
+template <class T>
+__device__ __forceinline__ T make_uniform(const T &v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+    T out;
+    const int *src = reinterpret_cast<const int *>(&v);
+    int *dst = reinterpret_cast<int *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+constexpr int CODE_OUT = -1;
+constexpr int CODE_SINGULAR = -2;
+
+template <bool UNIT>
+__device__ inline int exact_ray_thread(const RecheckArgs &a, int64_t i, int64_t j) {
+    const double x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
+    const double x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t k = 0; k < a.n_lens; ++k) {
+        const double d1 = x1 - a.lens_xy[2 * k];
+        const double d2 = x2 - a.lens_xy[2 * k + 1];
+        const double r2 = d1 * d1 + d2 * d2;
+        if (r2 == 0.0) return CODE_SINGULAR;
+        const double m = UNIT ? 1.0 : a.lens_m[k];
+        const double f = m / r2;
+        a1 += f * d1;
+        a2 += f * d2;
+    }
+    const double y1 = ((1.0 - a.gamma) - a.sigma_c) * x1 - a1;
+    const double y2 = ((1.0 + a.gamma) - a.sigma_c) * x2 - a2;
+    const double u = (y1 - a.tx0) / (a.tw / (double)a.npx);
+    const double v = (y2 - a.ty0) / (a.th / (double)a.npy);
+    if (isfinite(u) && isfinite(v) && u >= 0.0 && u < (double)a.npx && v >= 0.0 && v < (double)a.npy)
+        return (int)((int64_t)floor(v) * a.npx + (int64_t)floor(u));
+    return CODE_OUT;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The same definition evaluated by a whole wave for one ray (i, j wave-uniform):
+// lanes form the per-lens terms (m/r2)*d1, (m/r2)*d2 of 64 lenses at a time and
+// the lens-order sum adds them one by one.
+template <bool UNIT>
+__device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j) {
+    const int lane = __lane_id();
+    const double x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
+    const double x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t k0 = 0; k0 < a.n_lens; k0 += 64) {
+        const int64_t k = k0 + lane;
+        double t1 = 0.0, t2 = 0.0;
+        bool zero = false;
+        if (k < a.n_lens) {
+            const double d1 = x1 - a.lens_xy[2 * k];
+            const double d2 = x2 - a.lens_xy[2 * k + 1];
+            const double r2 = d1 * d1 + d2 * d2;
+            zero = (r2 == 0.0);
+            const double m = UNIT ? 1.0 : a.lens_m[k];
+            const double f = m / r2;
+            t1 = f * d1;
+            t2 = f * d2;
+        }
+        if (__ballot(zero)) return CODE_SINGULAR;
+        const int cnt = (a.n_lens - k0) < 64 ? (int)(a.n_lens - k0) : 64;
+        for (int l = 0; l < cnt; ++l) {
+            a1 += readlane_f64(t1, l);
+            a2 += readlane_f64(t2, l);
+        }
+    }
+    const double y1 = ((1.0 - a.gamma) - a.sigma_c) * x1 - a1;
+    const double y2 = ((1.0 + a.gamma) - a.sigma_c) * x2 - a2;
+    const double u = (y1 - a.tx0) / (a.tw / (double)a.npx);
+    const double v = (y2 - a.ty0) / (a.th / (double)a.npy);
+    if (isfinite(u) && isfinite(v) && u >= 0.0 && u < (double)a.npx && v >= 0.0 && v < (double)a.npy)
+        return (int)((int64_t)floor(v) * a.npx + (int64_t)floor(u));
+    return CODE_OUT;
+}
+
+// Stage A. Returns true (and the definition's code) when the ray is decided.
+template <bool UNIT>
+__device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
+    const double U64 = 1.1102230246251565e-16;  // 2^-53
+    const double x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
+    const double x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    const double c1 = (1.0 - a.gamma) - a.sigma_c;
+    const double c2 = (1.0 + a.gamma) - a.sigma_c;
+    const double inv_pixw = (double)a.npx / a.tw;
+    const double inv_pixh = (double)a.npy / a.th;
+    double a1 = 0.0, a2 = 0.0, S = 0.0;
+    bool tiny = false;
+#pragma unroll 4
+    for (int64_t k = 0; k < a.n_lens; ++k) {
+        const double d1 = x1 - a.lens_xy[2 * k];
+        const double d2 = x2 - a.lens_xy[2 * k + 1];
+        const double r2 = __builtin_fma(d1, d1, d2 * d2);
+        tiny |= !(r2 > 1e-200);
+        double rc = __builtin_amdgcn_rcp(r2);
+        double e = __builtin_fma(-r2, rc, 1.0);
+        rc = __builtin_fma(rc, e, rc);
+        e = __builtin_fma(-r2, rc, 1.0);
+        rc = __builtin_fma(rc, e, rc);
+        if (!UNIT) rc = rc * a.lens_m[k];
+        a1 = __builtin_fma(d1, rc, a1);
+        a2 = __builtin_fma(d2, rc, a2);
+        S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
+    }
+    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
+    const double u = (c1 * x1 - a1 - a.tx0) * inv_pixw;
+    const double v = (c2 * x2 - a2 - a.ty0) * inv_pixh;
+    const double Mu = 2.002 * (kN * S + 8.0 * U64 * (fabs(c1 * x1) + fabs(a1) + fabs(a.tx0))) * inv_pixw;
+    const double Mv = 2.002 * (kN * S + 8.0 * U64 * (fabs(c2 * x2) + fabs(a2) + fabs(a.ty0))) * inv_pixh;
+    const double fu = floor(u), fv = floor(v);
+    const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
+    const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
+    const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
+    const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
+    const bool sane = !tiny && isfinite(S) && isfinite(Mu) && isfinite(Mv);
+    if (sane && ok_u && ok_v) {
+        code = (int)((int64_t)fv * a.npx + (int64_t)fu);
+        return true;
+    }
+    if (sane && (out_u || out_v)) {
+        code = CODE_OUT;
+        return true;
+    }
+    return false;
+}
+
+// Bin one re-checked ray (or write its pixel) and count it in the map's counters.
+__device__ inline void emit_ray(const RecheckArgs &a, int64_t i, int64_t j, int code) {
+    if (a.pix_out) {
+        a.pix_out[(j - a.j0) * (a.i1 - a.i0) + (i - a.i0)] = code;
+    } else if (code >= 0) {
+        atomicAdd(a.map + code, 1u);
+    }
+    atomicAdd(a.counters + (code >= 0 ? C_IN : (code == CODE_OUT ? C_OUT : C_SING)), 1ull);
+}
+
+// Full re-check of one ray by one thread: stage A, then the exact sequence.
+__device__ inline int recheck_ray_thread(const RecheckArgs &a, int64_t i, int64_t j) {
+    int code = 0;
+    if (a.lens_m == nullptr) {
+        if (!fast_ray<true>(a, i, j, code)) code = exact_ray_thread<true>(a, i, j);
+    } else {
+        if (!fast_ray<false>(a, i, j, code)) code = exact_ray_thread<false>(a, i, j);
+    }
+    return code;
+}
+
+}  // namespace rs

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "rayshoot.h"
+
 namespace rs {
 
 // Ray patch of one block of the deflection kernel: PATCH_X x PATCH_Y rays,
@@ -32,6 +34,7 @@ constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] queue lengths
 constexpr int64_t CHUNK_RAYS = int64_t(1) << 27;  // rays per launch (queue capacity)
 
 enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3 };
+constexpr int N_COUNTERS = 8;
 
 struct ShootArgs {
     // Ray grid: x1 = sx0 + ((double)i + 0.5) * spx (the same FP64 operations
@@ -75,9 +78,138 @@ struct RecheckArgs {
     const uint32_t *qcount;
 };
 
+// Shoot arguments of a whole window (no chunking): the same values the host
+// computes for a single map, by the same IEEE operations, on host or device.
+__host__ __device__ inline ShootArgs shoot_args_of(const rs_map_params &p, const double *lens_xy,
+                                                   const double *lens_m, int64_t n_lens, uint32_t *map,
+                                                   unsigned long long *counters) {
+    ShootArgs a{};
+    a.sx0 = p.sx0;
+    a.sy0 = p.sy0;
+    a.spx = p.sw / (double)p.nx;
+    a.spy = p.sh / (double)p.ny;
+    a.i0 = p.i0;
+    a.i1 = p.i1;
+    a.jc0 = p.j0;
+    a.jc1 = p.j1;
+    a.j0 = p.j0;
+    a.nbx = (p.i1 - p.i0 + PATCH_X - 1) / PATCH_X;
+    a.c1 = (1.0 - p.gamma) - p.sigma_c;
+    a.c2 = (1.0 + p.gamma) - p.sigma_c;
+    a.tx0 = p.tx0;
+    a.ty0 = p.ty0;
+    a.inv_pixw = (double)p.npx / p.tw;
+    a.inv_pixh = (double)p.npy / p.th;
+    a.npx = p.npx;
+    a.npy = p.npy;
+    a.lens_xy = lens_xy;
+    a.lens_m = lens_m;
+    a.n_lens = n_lens;
+    a.bound_scale = 1.0 + (double)(n_lens + 64) * 4.7e-10;
+    a.map = map;
+    a.pix_out = nullptr;
+    a.counters = counters;
+    a.queue = nullptr;
+    a.qcount = nullptr;
+    return a;
+}
+
+__host__ __device__ inline RecheckArgs recheck_args_of(const rs_map_params &p, const double *lens_xy,
+                                                       const double *lens_m, int64_t n_lens, uint32_t *map,
+                                                       unsigned long long *counters) {
+    RecheckArgs r{};
+    r.sx0 = p.sx0;
+    r.sy0 = p.sy0;
+    r.sw = p.sw;
+    r.sh = p.sh;
+    r.nx = p.nx;
+    r.ny = p.ny;
+    r.i0 = p.i0;
+    r.i1 = p.i1;
+    r.jc0 = p.j0;
+    r.j0 = p.j0;
+    r.gamma = p.gamma;
+    r.sigma_c = p.sigma_c;
+    r.tx0 = p.tx0;
+    r.ty0 = p.ty0;
+    r.tw = p.tw;
+    r.th = p.th;
+    r.npx = p.npx;
+    r.npy = p.npy;
+    r.lens_xy = lens_xy;
+    r.lens_m = lens_m;
+    r.n_lens = n_lens;
+    r.map = map;
+    r.pix_out = nullptr;
+    r.counters = counters;
+    r.queue = nullptr;
+    r.qcount = nullptr;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Batched maps: one persistent launch over the patches of many maps.
+// ---------------------------------------------------------------------------
+
+// Per-map descriptor in device memory (work order: most expensive maps first).
+struct BatchMap {
+    rs_map_params p;
+    const double *lens_xy;
+    const double *lens_m;
+    int64_t n_lens;
+    uint32_t *map;
+    unsigned long long *counters;  // N_COUNTERS per map, in the workspace (request order)
+    int64_t tile_begin;            // first tile of this map in the work list
+    int64_t n_tiles;
+    uint32_t *flag_bits;           // one bit per ray of the window: re-check this ray
+    uint32_t *unres_bits;          // one bit per ray: stage A could not place it
+    int64_t word_begin;            // first bitmap word of this map in the batch's word space
+    int64_t n_words;               // bitmap words, a multiple of 64
+    int32_t request;               // index of the request this map came from
+    int32_t accumulate;            // keep the map's contents (RS_ACCUMULATE)
+};
+
+struct QueueEntry {
+    uint32_t map;   // index into the BatchMap array
+    uint32_t ray;   // (j - j0) * (i1 - i0) + (i - i0)
+};
+
+struct BatchArgs {
+    const BatchMap *maps;
+    int32_t n_maps;
+    int32_t mode;
+    int32_t unit_masses;           // every map of the batch has unit masses
+    int32_t pad;
+    int64_t total_tiles;
+    int64_t total_words;
+    unsigned long long *tile_counter;
+    unsigned int *unresolved;          // set when stage A left a ray to the exact stage
+};
+
+// Batch workspace layout (bytes):
+//   [globals 256: uint64 tile counter, uint32 unresolved flag]
+//   [BatchMap x n][counters 64 x n][flag bitmaps][unresolved bitmaps]
+constexpr size_t BWS_GLOBALS = 256;
+constexpr int64_t BITMAP_WORD_ALIGN = 64;   // a 64-word scan block never straddles two maps
+inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+inline size_t batch_maps_offset() { return BWS_GLOBALS; }
+inline size_t batch_counters_offset(int32_t n) { return align256(BWS_GLOBALS + sizeof(BatchMap) * (size_t)n); }
+inline size_t batch_bitmaps_offset(int32_t n) {
+    return align256(batch_counters_offset(n) + sizeof(unsigned long long) * N_COUNTERS * (size_t)n);
+}
+inline int64_t bitmap_words_of(const rs_map_params &p) {
+    const int64_t rays = (p.i1 - p.i0) * (p.j1 - p.j0);
+    const int64_t words = (rays + 31) / 32;
+    return (words + BITMAP_WORD_ALIGN - 1) / BITMAP_WORD_ALIGN * BITMAP_WORD_ALIGN;
+}
+
 hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_qcount,
                        hipStream_t stream);
 hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream);
 hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);
+
+hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream);
+hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream);
+hipError_t launch_recheck_batch(const BatchArgs &b, hipStream_t stream);
 
 }  // namespace rs

@@ -88,6 +88,32 @@ struct Profile {
 };
 static Profile g_prof;
 
+// Kernel timing hooks: when profiling is on, record an event pair around a launch.
+void profile_begin(hipStream_t stream, void **token) {
+    *token = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.on) return;
+    }
+    hipEvent_t a = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventRecord(a, stream) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    *token = a;
+}
+
+int profile_end(hipStream_t stream, void *token, double interactions) {
+    if (!token) return RS_OK;
+    hipEvent_t a = static_cast<hipEvent_t>(token), b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, stream) != hipSuccess)
+        return fail(RS_EHIP, "hipEventRecord failed");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({a, b, interactions});
+    return RS_OK;
+}
+
 int choose_shape(int mode, bool unit, int64_t n_lens);
 
 // Enqueue the whole map (or pixel) computation. map may be null when pix is set.
@@ -164,11 +190,6 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
     r.counters = a.counters;
     r.queue = a.queue;
 
-    bool prof;
-    {
-        std::lock_guard<std::mutex> lk(g_prof.mu);
-        prof = g_prof.on;
-    }
     if (shape < 0) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
     hipEvent_t t_first = nullptr, t_last = nullptr;
     if (kernel_ms) {
@@ -181,12 +202,8 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         a.jc0 = p->j0 + c * pl.rows_per_chunk;
         a.jc1 = a.jc0 + pl.rows_per_chunk < p->j1 ? a.jc0 + pl.rows_per_chunk : p->j1;
         a.qcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + c;
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (prof) {
-            if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-                return fail(RS_EHIP, "hipEventCreate failed");
-            if (hipEventRecord(ev0, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
-        }
+        void *tok = nullptr;
+        profile_begin(stream, &tok);
         if (kernel_ms && hipEventRecord(t_first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
         e = launch_shoot(a, p->mode, shape, stream);
         if (e != hipSuccess) return hip_fail(e, "deflection kernel");
@@ -197,11 +214,8 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
                 return fail(RS_EHIP, "timing the deflection kernel failed");
             timed_ms += ms;
         }
-        if (prof) {
-            if (hipEventRecord(ev1, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
-            std::lock_guard<std::mutex> lk(g_prof.mu);
-            g_prof.pending.push_back({ev0, ev1, (double)(a.jc1 - a.jc0) * (double)pl.W * (double)n_lens});
-        }
+        rc = profile_end(stream, tok, (double)(a.jc1 - a.jc0) * (double)pl.W * (double)n_lens);
+        if (rc) return rc;
         if (p->mode == RS_MIXED) {
             r.jc0 = a.jc0;
             r.qcount = a.qcount;

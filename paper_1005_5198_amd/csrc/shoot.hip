@@ -23,7 +23,7 @@
 //    queue that an FP64 kernel re-evaluates with the plain definition.
 //  * Binning uses wave-aggregated atomics: lanes that hit the same pixel add
 //    their count with one atomic.
-#include "rs_internal.h"
+#include "recheck_ray.h"
 
 namespace rs {
 namespace {
@@ -69,29 +69,68 @@ __device__ __forceinline__ void aggregated_add(uint32_t *map, int p) {
     }
 }
 
-// RX x RY rays per lane, WX x WY waves per block; every shape covers the same
-// PATCH_X x PATCH_Y ray patch, so a ray's arithmetic (patch origin, lens
-// offsets, operation order) does not depend on the shape chosen.
-template <int RX, int RY, int WX, int WY, bool UNIT, int MODE, bool PIX>
-__global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) {
+struct ShootSmem {
+    float4 tile[LENS_TILE];        // UNIT: two (x,y) pairs per float4; else (x,y,m,0)
+    NearLens near_list[NEAR_MAX];
+    int near_count;
+    double red_bx[16], red_by[16];
+};
+
+// Queue sink of a single-map launch: uint32 chunk-relative ray indices; the
+// queue holds every ray of the launch, so it cannot overflow.
+struct SingleSink {
+    __device__ void append(const ShootArgs &a, uint64_t fl, int lane, bool mine, int64_t i, int64_t j) const {
+        const int first = __builtin_ctzll(fl);
+        uint32_t base = 0;
+        if (lane == first) base = atomicAdd(a.qcount, (uint32_t)__builtin_popcountll(fl));
+        base = __builtin_amdgcn_readlane(base, first);
+        if (mine) {
+            const uint32_t below = (uint32_t)__builtin_popcountll(fl & ((1ull << lane) - 1ull));
+            a.queue[base + below] = (uint32_t)((j - a.jc0) * (a.i1 - a.i0) + (i - a.i0));
+        }
+    }
+};
+
+// Re-check sink of a batch launch: one bit per flagged ray in the map's flag
+// bitmap (two bits per ray of workspace in all, whatever the flagged fraction).
+struct BatchSink {
+    unsigned long long *counters;
+    uint32_t *flag_bits;
+    __device__ void append(const ShootArgs &a, uint64_t fl, int lane, bool mine, int64_t i, int64_t j) const {
+        if (lane == __builtin_ctzll(fl)) atomicAdd(counters + C_RECHECK, (unsigned long long)__builtin_popcountll(fl));
+        if (mine) {
+            const uint32_t ray = (uint32_t)((j - a.j0) * (a.i1 - a.i0) + (i - a.i0));
+            atomicOr(flag_bits + (ray >> 5), 1u << (ray & 31u));
+        }
+    }
+};
+
+// One 64 x 32 ray patch. RX x RY rays per lane, WX x WY waves per block; every
+// shape covers the same PATCH_X x PATCH_Y ray patch, so a ray's arithmetic
+// (patch origin, lens offsets, operation order) does not depend on the shape.
+template <int RX, int RY, int WX, int WY, bool UNIT, int MODE, bool PIX, class Sink>
+__device__ __forceinline__ void shoot_patch(const ShootArgs &a, int64_t patch, ShootSmem &sm, const Sink &sink) {
     constexpr int BLOCK_THREADS = 64 * WX * WY;
     constexpr int STRIDE_X = LANES_X * WX;
     constexpr int STRIDE_Y = LANES_Y * WY;
     static_assert(RX * STRIDE_X == PATCH_X && RY * STRIDE_Y == PATCH_Y, "shape must tile the patch");
-    __shared__ float4 tile[LENS_TILE];        // UNIT: two (x,y) pairs per float4; else (x,y,m,0)
-    __shared__ NearLens near_list[NEAR_MAX];
-    __shared__ int near_count;
-    __shared__ double red_bx[BLOCK_THREADS / 64], red_by[BLOCK_THREADS / 64];
+    static_assert(BLOCK_THREADS / 64 <= 16, "reduction buffer");
+    float4 *tile = sm.tile;
+    NearLens *near_list = sm.near_list;
+    int &near_count = sm.near_count;
+    double *red_bx = sm.red_bx;
+    double *red_by = sm.red_by;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int wx = wave % WX, wy = wave / WX;
     const int lx = lane % LANES_X, ly = lane / LANES_X;
+    __syncthreads();  // the previous patch of this block is done with the shared buffers
 
     // Patch of this block.
-    const int64_t pbx = blockIdx.x % a.nbx;
-    const int64_t pby = blockIdx.x / a.nbx;
+    const int64_t pbx = patch % a.nbx;
+    const int64_t pby = patch / a.nbx;
     const int64_t ib = a.i0 + pbx * PATCH_X;
     const int64_t jb = a.jc0 + pby * PATCH_Y;
     // Patch origin and half-extents (with a spacing of slack on each side).
@@ -135,7 +174,7 @@ __global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) 
                 const int64_t k = t0 + s;
                 const double X = a.lens_xy[2 * k];
                 const double Y = a.lens_xy[2 * k + 1];
-                const double m = UNIT ? 1.0 : a.lens_m[k];
+                const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
                 const double Lx = X - ox, Ly = Y - oy;
                 fx = (float)Lx;
                 fy = (float)Ly;
@@ -328,16 +367,7 @@ __global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) 
             }
             if (MODE == 1) {
                 const uint64_t fl = __ballot(code == FLAGGED);
-                if (fl) {
-                    const int first = __builtin_ctzll(fl);
-                    uint32_t base = 0;
-                    if (lane == first) base = atomicAdd(a.qcount, (uint32_t)__builtin_popcountll(fl));
-                    base = __builtin_amdgcn_readlane(base, first);
-                    if (code == FLAGGED) {
-                        const uint32_t below = (uint32_t)__builtin_popcountll(fl & ((1ull << lane) - 1ull));
-                        a.queue[base + below] = (uint32_t)((j - a.jc0) * W + (i - a.i0));
-                    }
-                }
+                if (fl) sink.append(a, fl, lane, code == FLAGGED, i, j);
             }
         }
     if (lane == 0) {
@@ -345,6 +375,61 @@ __global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) 
         if (n_out) atomicAdd(a.counters + C_OUT, n_out);
         if (n_sing) atomicAdd(a.counters + C_SING, n_sing);
     }
+}
+
+// Single map: one block per patch of this launch's rows.
+template <int RX, int RY, int WX, int WY, bool UNIT, int MODE, bool PIX>
+__global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) {
+    __shared__ ShootSmem sm;
+    shoot_patch<RX, RY, WX, WY, UNIT, MODE, PIX>(a, (int64_t)blockIdx.x, sm, SingleSink{});
+}
+
+// Batch: persistent blocks pull (map, patch) tiles from one counter until the
+// work list is exhausted; every block exits when the counter passes the end.
+template <int RX, int RY, int WX, int WY, bool UNIT, int MODE>
+__global__ __launch_bounds__(64 * WX * WY, (RX * RY <= 8) ? 4 : 1) void shoot_batch_kernel(const BatchArgs b) {
+    __shared__ ShootSmem sm;
+    __shared__ long long s_tile;
+    for (;;) {
+        __syncthreads();  // s_tile of the previous round has been read by every thread
+        if (threadIdx.x == 0) s_tile = (long long)atomicAdd(b.tile_counter, 1ull);
+        __syncthreads();
+        // The tile index is the same for the whole block; make that visible to the
+        // compiler so per-map values live in scalar registers.
+        const unsigned long long st = (unsigned long long)s_tile;
+        const unsigned t_lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)st);
+        const unsigned t_hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(st >> 32));
+        const long long t = (long long)(((unsigned long long)t_hi << 32) | t_lo);
+        if (t >= b.total_tiles) break;
+        int lo = 0, hi = b.n_maps - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.maps[mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchMap &m = b.maps[lo];
+        const ShootArgs a = make_uniform(shoot_args_of(m.p, m.lens_xy, m.lens_m, m.n_lens, m.map, m.counters));
+        const int64_t tile_begin = make_uniform(m.tile_begin);
+        uint32_t *const bits = make_uniform(m.flag_bits);
+        const BatchSink sink{a.counters, bits};
+        shoot_patch<RX, RY, WX, WY, UNIT, MODE, false>(a, t - tile_begin, sm, sink);
+    }
+}
+
+// Zero each map of a batch (unless it accumulates), its counters, and the batch globals.
+__global__ void fill_batch_kernel(const BatchArgs b, unsigned long long *globals) {
+    const int mi = blockIdx.y;
+    const BatchMap &m = b.maps[mi];
+    if (blockIdx.x == 0 && threadIdx.x < N_COUNTERS) m.counters[threadIdx.x] = 0ull;
+    if (mi == 0 && blockIdx.x == 0 && threadIdx.x < 4) globals[threadIdx.x] = 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m.n_words; t += stride) {
+        m.flag_bits[t] = 0u;
+        m.unres_bits[t] = 0u;
+    }
+    if (m.accumulate) return;
+    const int64_t n = m.p.npx * m.p.npy;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) m.map[t] = 0u;
 }
 
 __global__ void fill_kernel(uint32_t *map, int64_t n_pix, uint32_t *ws_words, int64_t n_ws_words) {
@@ -389,6 +474,61 @@ const ShapeInfo &shape_info(int shape) {
         {4, 2, 2, 2}, {4, 4, 2, 1}, {8, 2, 1, 2}, {8, 4, 1, 1},
     };
     return table[(shape >= 0 && shape < N_SHAPES) ? shape : 0];
+}
+
+// Resident blocks of a persistent kernel: every CU times the blocks that fit on it.
+template <class K>
+static int resident_blocks(K kernel, int threads) {
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+            n_cu = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 2;
+    return n_cu * per_cu;
+}
+
+template <int RX, int RY, int WX, int WY, bool UNIT, int MODE>
+static void launch_batch_variant(const BatchArgs &b, int grid_blocks, hipStream_t stream) {
+    const int threads = 64 * WX * WY;
+    auto k = shoot_batch_kernel<RX, RY, WX, WY, UNIT, MODE>;
+    if (grid_blocks <= 0) grid_blocks = resident_blocks(k, threads);
+    if ((int64_t)grid_blocks > b.total_tiles) grid_blocks = (int)b.total_tiles;
+    hipLaunchKernelGGL(k, dim3((unsigned)grid_blocks), dim3(threads), 0, stream, b);
+}
+
+template <int RX, int RY, int WX, int WY>
+static void launch_batch_shape(const BatchArgs &b, int grid_blocks, hipStream_t stream) {
+    if (b.unit_masses) {
+        if (b.mode == 0) launch_batch_variant<RX, RY, WX, WY, true, 0>(b, grid_blocks, stream);
+        else launch_batch_variant<RX, RY, WX, WY, true, 1>(b, grid_blocks, stream);
+    } else {
+        if (b.mode == 0) launch_batch_variant<RX, RY, WX, WY, false, 0>(b, grid_blocks, stream);
+        else launch_batch_variant<RX, RY, WX, WY, false, 1>(b, grid_blocks, stream);
+    }
+}
+
+hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream) {
+    if (b.total_tiles <= 0) return hipSuccess;
+    switch (shape) {
+        case 1: launch_batch_shape<4, 4, 2, 1>(b, grid_blocks, stream); break;
+        case 2: launch_batch_shape<8, 2, 1, 2>(b, grid_blocks, stream); break;
+        case 3: launch_batch_shape<8, 4, 1, 1>(b, grid_blocks, stream); break;
+        default: launch_batch_shape<4, 2, 2, 2>(b, grid_blocks, stream); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream) {
+    if (n_maps <= 0) return hipSuccess;
+    const dim3 grid(64, (unsigned)n_maps), block(256);
+    hipLaunchKernelGGL(fill_batch_kernel, grid, block, 0, stream, b,
+                       static_cast<unsigned long long *>(workspace));
+    return hipGetLastError();
 }
 
 hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream) {

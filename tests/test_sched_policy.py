@@ -1,0 +1,63 @@
+"""The request loop's scheduling policy on the CPU (simulated time; no device).
+
+tests/sched_driver.cpp links only paper_1005_5198_amd/csrc/rs_sched.h (pure host
+logic) and prints the outcomes checked here.
+"""
+import json
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def res(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("sched") / "sched_driver")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", "-fsanitize=address,undefined",
+                    "-I", os.path.join(ROOT, "paper_1005_5198_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "sched_driver.cpp"), "-o", exe], check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return json.loads(out)
+
+
+def test_admission_by_footprint_fifo(res):
+    assert res["admit1"] == [1, 2]          # 600 + 300 fit 1000; 200 does not
+    assert res["done1"] == [1, 2]           # both finished in one big step
+    assert res["admit2"] == [3, 4]          # then 3 (not overtaken by 4) and 4
+    assert res["rejected"] == [5]           # larger than the whole budget
+    assert res["plan1_rows_quantum"]
+
+
+def test_slot_limit(res):
+    assert res["slots_admit"] == [1, 2] and res["slots_waiting"] == 3
+
+
+def test_fair_slicing(res):
+    step1 = res["fair_step1"]
+    assert [s[0] for s in step1] == [1, 2]
+    assert step1[0][1:] == [0, 64, 1] and step1[1][1:] == [0, 64, 1]
+    assert res["fair_done1"] == []
+    assert res["fair_step2_n"] == 2 and res["fair_step2_first"] == 64
+    assert res["fair_done2"] == [2]         # 70 rows: done after its second slice
+    # work-conserving: once job 2 is done, job 1 gets the whole step (128 rows)
+    assert res["fair_total_steps"] == 2 + -(-(1000 - 128) // 128)
+
+
+def test_cancellation(res):
+    assert res["cancel_dropped"] == [2]
+    assert res["cancel_plan_after"] == 0    # a cancelled job gets no more slices
+    assert res["cancel_reaped"] == 1 and res["cancel_reaped_flag"]
+    assert res["cancel_active_left"] == 0
+
+
+def test_arena(res):
+    assert res["arena_three"] and not res["arena_full"]
+    assert res["arena_hole"] == 1024        # 4096 - 3*1024 = 1024 tail; hole of 1024
+    assert res["arena_coalesced"] == 2048
+    assert res["arena_empty"] == 4096 and res["arena_in_use"] == 0 and res["arena_peak"] == 3072
+
+
+def test_percentiles(res):
+    assert float(res["p50"]) == 50.0 and float(res["p99"]) == 99.0 and float(res["p100"]) == 100.0
