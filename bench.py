@@ -14,8 +14,10 @@ Prints ONE JSON line:
               the kernel's stream), against the 157.3 TFLOP/s FP32 peak
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample
               of the same map (a band of ray rows)
-Also reported: the plain-FP32 mode rate, the re-check fraction, and the
-batched and served comparisons when --batched/--serve are given.
+Also reported: the plain-FP32 mode rate, the re-check fraction, the 64-map
+batch (one persistent launch) against the same maps one at a time, and the
+request loop (continuous batching, Poisson arrivals) against the same arrivals
+served one at a time, with maps/s and p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -46,8 +48,10 @@ def parse():
     ap.add_argument("--mode", default="mixed", choices=("mixed", "fp32"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--batched", action="store_true", help="also time the 64-map batch")
-    ap.add_argument("--serve", action="store_true", help="also run the serving loop")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-map batch vs one-at-a-time")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request loop vs one-at-a-time")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rho", type=float, default=0.8)
     return ap.parse_args()
 
 
@@ -149,12 +153,13 @@ def main():
             rs.make_map(spec.params, xy, m, mode="fp32", out=out, workspace=ws32)
         torch.cuda.synchronize()
         result["fp32_mode_value"] = inter * n32 / (time.perf_counter() - t)
-    if args.batched or args.serve:
+    if not (args.no_batched and args.no_serve):
         from paper_1005_5198_amd import bench_extra
-        if args.batched:
-            result["batched"] = bench_extra.batched(rs)
-        if args.serve:
-            result["served"] = bench_extra.served(rs)
+        if not args.no_batched:
+            result["batched"] = bench_extra.batched(rs, mode=args.mode)
+        if not args.no_serve:
+            result["served"] = bench_extra.served(rs, n_requests=args.serve_requests, rho=args.serve_rho,
+                                                  mode=args.mode)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(result), flush=True)

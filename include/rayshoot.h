@@ -228,9 +228,11 @@ int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_ho
 /* Request loop with continuous batching.                                      */
 /* A scheduler thread admits requests in arrival order when a slot is free and */
 /* their device footprint (lenses, masses, map) fits the server's pool, and    */
-/* keeps two launch steps in flight: each step gives every active request one  */
-/* band of ray rows and runs them all as one rs_make_maps batch. A request that */
-/* arrives while the GPU is busy joins the next step. Each finished map equals  */
+/* keeps two launch steps in flight. Each step hands out about slice_ms of GPU  */
+/* work as bands of ray rows, least remaining work first (every active request */
+/* gets at least one 32-row band), and runs them as one rs_make_maps batch. A  */
+/* request that arrives while the GPU is busy joins the next step; a small one */
+/* then finishes without waiting for large ones. Each finished map equals      */
 /* rs_make_map of the same request bit for bit (a map is the integer sum of its */
 /* bands).                                                                      */
 /* ------------------------------------------------------------------------- */
@@ -239,7 +241,7 @@ typedef struct {
     size_t hbm_budget_bytes;  /* device pool for admitted requests (allocated once, by the server) */
     int32_t max_inflight;     /* requests admitted at once (slots), >= 1 */
     int32_t mode;             /* RS_FP32 or RS_MIXED, for every request */
-    double slice_ms;          /* target GPU time of one launch step; <= 0 selects 20 ms */
+    double slice_ms;          /* target GPU time of one launch step; <= 0 selects 10 ms */
 } rs_server_cfg;
 
 typedef struct {

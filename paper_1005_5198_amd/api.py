@@ -227,7 +227,7 @@ class Server:
     """The request loop (continuous batching). Inputs are host arrays; results come back as numpy maps."""
 
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_inflight: int = 16, mode: str = "mixed",
-                 slice_ms: float = 20.0):
+                 slice_ms: float = 10.0):
         _device()
         cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms))
         h = ctypes.c_void_p()

@@ -62,7 +62,7 @@ def _percentiles(lat):
 
 
 def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed: int = 4,
-           budget_bytes: int = 2 << 30, max_inflight: int = 16, slice_ms: float = 20.0) -> dict:
+           budget_bytes: int = 2 << 30, max_inflight: int = 16, slice_ms: float = 10.0) -> dict:
     """Poisson arrivals of config-3-distributed requests (each with its own lens set):
     the request loop vs the same arrivals served one at a time by plain rs_make_map calls."""
     import threading
@@ -73,11 +73,13 @@ def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed
         out = rs.make_map(s.params, s.lens_xy, s.lens_m, mode=mode)
         return out.cpu().numpy()
     plain_one(specs[0])
+    head = specs[: min(8, n_requests)]
     t = time.perf_counter()
-    for s in specs[: min(8, n_requests)]:
+    for s in head:
         plain_one(s)
-    plain_rate = min(8, n_requests) / (time.perf_counter() - t)
-    rate = rho * plain_rate
+    plain_ips = sum(s.interactions for s in head) / (time.perf_counter() - t)
+    mean_inter = sum(s.interactions for s in specs) / n_requests
+    rate = rho * plain_ips / mean_inter          # requests per second at load rho
     gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=n_requests)
     arrivals = np.cumsum(gaps) - gaps[0]
 

@@ -205,6 +205,7 @@ inline int64_t bitmap_words_of(const rs_map_params &p) {
 
 hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_qcount,
                        hipStream_t stream);
+hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream);
 hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);
 

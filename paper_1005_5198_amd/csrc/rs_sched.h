@@ -137,24 +137,33 @@ class Policy {
         return out;
     }
 
-    // Next step: every active job with rows left gets one slice, sized so the
-    // step holds about `target_interactions` ray-lens pairs shared equally.
-    std::vector<Slice> plan(double target_interactions) {
+    // Next step, holding about `target_interactions` ray-lens pairs. The budget
+    // goes to open jobs in order of least remaining work, discounted by age:
+    // remaining / (1 + waited / aging_s). A small request finishes in the next
+    // step instead of queueing behind a large one, and a large one that has
+    // waited long gains priority. Every open job gets at least one 32-row band
+    // per step, so none starves.
+    std::vector<Slice> plan(double target_interactions, double now = 0.0, double aging_s = 0.25) {
         std::vector<Slice> step;
-        int n_open = 0;
-        for (const Job &j : active_)
-            if (!j.cancel && j.next_row < j.rows) ++n_open;
-        if (n_open == 0) return step;
-        const double share = target_interactions / n_open;
-        for (Job &j : active_) {
-            if (j.cancel || j.next_row >= j.rows) continue;
-            const double per_row = (double)j.width * (double)std::max<int64_t>(j.n_lens, 1);
-            int64_t rows = (int64_t)(share / per_row);
+        std::vector<Job *> open;
+        for (Job &j : active_)
+            if (!j.cancel && j.next_row < j.rows) open.push_back(&j);
+        if (open.empty()) return step;
+        auto per_row = [](const Job *j) { return (double)j->width * (double)std::max<int64_t>(j->n_lens, 1); };
+        auto key = [&](const Job *j) {
+            const double waited = now > j->t_submit ? now - j->t_submit : 0.0;
+            return per_row(j) * (double)(j->rows - j->next_row) / (1.0 + waited / aging_s);
+        };
+        std::stable_sort(open.begin(), open.end(), [&](const Job *a, const Job *b) { return key(a) < key(b); });
+        double left = target_interactions;
+        for (Job *j : open) {
+            int64_t rows = left > 0 ? (int64_t)(left / per_row(j)) : 0;
             rows = std::max<int64_t>(ROW_QUANTUM, rows / ROW_QUANTUM * ROW_QUANTUM);
-            const int64_t row1 = std::min(j.rows, j.next_row + rows);
-            step.push_back(Slice{j.ticket, j.next_row, row1, j.next_row == 0});
-            j.next_row = row1;
-            ++j.steps_in_flight;
+            const int64_t row1 = std::min(j->rows, j->next_row + rows);
+            left -= per_row(j) * (double)(row1 - j->next_row);
+            step.push_back(Slice{j->ticket, j->next_row, row1, j->next_row == 0});
+            j->next_row = row1;
+            ++j->steps_in_flight;
         }
         return step;
     }

@@ -3,9 +3,12 @@
 // launch steps; each step gives every active request one slice (a band of ray
 // rows) and runs all slices as one batched launch (rs_make_maps: persistent
 // deflection kernel + FP64 re-check). Requests that arrive while a step runs
-// join the next one. Two steps are kept in flight on the compute stream;
-// finished maps are copied out on a second stream. A map is the integer sum
-// of its slices, so every result is bit-identical to the same map made alone.
+// join the next one. Two steps are kept in flight, on two streams, so the next
+// step's blocks fill the GPU while the previous one drains. Lens sets are
+// uploaded and maps zeroed at admission on a third stream; every slice then
+// adds into its map with integer atomics, so slices of one map may overlap in
+// time. Finished maps are copied out on a fourth stream. A map is the integer
+// sum of its slices, so every result is bit-identical to the same map made alone.
 #include "rs_internal.h"
 #include "rayshoot.h"
 #include "rs_sched.h"
@@ -74,7 +77,16 @@ struct rs_server {
     Policy policy;
     Arena arena;
     char *pool = nullptr;
-    hipStream_t compute = nullptr, copy = nullptr;
+    hipStream_t step_stream[2] = {nullptr, nullptr};  // alternate launch steps
+    hipStream_t admit = nullptr;                       // lens uploads, map zeroing
+    hipStream_t copy = nullptr;                        // stats and maps back to the host
+    hipEvent_t admitted_ev = nullptr;                  // last admission work
+    struct Retired {
+        hipEvent_t ev;
+        double interactions;
+    };
+    std::deque<Retired> recent;                        // ends of the last retired steps
+    bool admit_pending = false;
     int device = 0;
 
     std::mutex mu;
@@ -129,8 +141,8 @@ void rs_server::finish(Request &r, int state, int error) {
 
 // Plan and enqueue one step (called with the lock held). Returns false if there was nothing to run.
 bool rs_server::launch_step() {
-    const double target = rate * (cfg.slice_ms > 0 ? cfg.slice_ms : 20.0) * 1e-3;
-    std::vector<Slice> slices = policy.plan(target);
+    const double target = rate * (cfg.slice_ms > 0 ? cfg.slice_ms : 10.0) * 1e-3;
+    std::vector<Slice> slices = policy.plan(target, now_s());
     if (slices.empty()) return false;
     std::vector<rs_map_request> batch;
     batch.reserve(slices.size());
@@ -141,7 +153,7 @@ bool rs_server::launch_step() {
         q.params = r.p;
         q.params.j0 = r.p.j0 + s.row0;
         q.params.j1 = r.p.j0 + s.row1;
-        q.params.flags = (r.p.flags & RS_EXACT_RECHECK) | (s.first ? 0 : RS_ACCUMULATE);
+        q.params.flags = (r.p.flags & RS_EXACT_RECHECK) | RS_ACCUMULATE;  // zeroed at admission
         q.params.mode = cfg.mode;
         q.lens_xy = r.n_lens ? reinterpret_cast<const double *>(pool + r.off_lens) : nullptr;
         q.lens_m = r.has_m ? reinterpret_cast<const double *>(pool + r.off_m) : nullptr;
@@ -165,12 +177,21 @@ bool rs_server::launch_step() {
         if (hipMalloc(&ws[st.ws_index], bytes) != hipSuccess) rc = RS_EHIP;
         else ws_bytes[st.ws_index] = bytes;
     }
+    hipStream_t stream = step_stream[st.ws_index];
+    if (rc == RS_OK && admit_pending) {
+        // the maps and lenses this step uses were prepared on the admission stream
+        if (hipEventRecord(admitted_ev, admit) != hipSuccess ||
+            hipStreamWaitEvent(step_stream[0], admitted_ev, 0) != hipSuccess ||
+            hipStreamWaitEvent(step_stream[1], admitted_ev, 0) != hipSuccess)
+            rc = RS_EHIP;
+        admit_pending = false;
+    }
     if (rc == RS_OK && (hipEventCreate(&st.ev_start) != hipSuccess || hipEventCreate(&st.ev_end) != hipSuccess ||
-                        hipEventRecord(st.ev_start, compute) != hipSuccess))
+                        hipEventRecord(st.ev_start, stream) != hipSuccess))
         rc = RS_EHIP;
     if (rc == RS_OK)
-        rc = rs_make_maps(batch.data(), (int32_t)batch.size(), ws[st.ws_index], ws_bytes[st.ws_index], compute);
-    if (rc == RS_OK && hipEventRecord(st.ev_end, compute) != hipSuccess) rc = RS_EHIP;
+        rc = rs_make_maps(batch.data(), (int32_t)batch.size(), ws[st.ws_index], ws_bytes[st.ws_index], stream);
+    if (rc == RS_OK && hipEventRecord(st.ev_end, stream) != hipSuccess) rc = RS_EHIP;
     if (rc != RS_OK) {
         // the step could not run: fail its requests
         for (const Slice &s : slices) {
@@ -190,11 +211,27 @@ bool rs_server::launch_step() {
 }
 
 void rs_server::retire_step(Step &s) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, s.ev_start, s.ev_end) == hipSuccess && ms > 0.0f) {
-        gpu_busy_s += ms * 1e-3;
-        const double r = s.interactions / (ms * 1e-3);
-        if (s.interactions > 1e9) rate = 0.7 * rate + 0.3 * r;
+    // Device throughput from retirements: interactions of the last steps over the
+    // GPU time between their ends (exact while the pipeline is busy; low when it
+    // idles, which only makes the next steps smaller).
+    float own = 0.0f;
+    if (hipEventElapsedTime(&own, s.ev_start, s.ev_end) == hipSuccess && own > 0.0f) gpu_busy_s += own * 1e-3;
+    const hipEvent_t end_ev = s.ev_end;  // kept in `recent`, destroyed when it leaves
+    recent.push_back({end_ev, s.interactions});
+    s.ev_end = nullptr;
+    while (recent.size() > 8) {
+        (void)hipEventDestroy(recent.front().ev);
+        recent.pop_front();
+    }
+    if (recent.size() >= 3) {
+        float span = 0.0f;
+        double work = 0.0;
+        for (size_t k = 1; k < recent.size(); ++k) work += recent[k].interactions;
+        if (hipEventElapsedTime(&span, recent.front().ev, recent.back().ev) == hipSuccess && span > 0.0f &&
+            work > 1e9) {
+            const double r = work / (span * 1e-3);
+            rate = std::min(2e13, std::max(1e12, r));
+        }
     }
     interactions += s.interactions;
     // per-slice counters of this step, in slice order
@@ -220,7 +257,7 @@ void rs_server::retire_step(Step &s) {
         int err = r.error;
         if (err == RS_OK && r.map_host) {
             const size_t bytes = 4 * (size_t)(r.p.npx * r.p.npy);
-            if (hipStreamWaitEvent(copy, s.ev_end, 0) != hipSuccess ||
+            if (hipStreamWaitEvent(copy, end_ev, 0) != hipSuccess ||
                 hipMemcpyAsync(r.map_host, pool + r.off_map, bytes, hipMemcpyDeviceToHost, copy) != hipSuccess ||
                 hipStreamSynchronize(copy) != hipSuccess)
                 err = RS_EHIP;
@@ -228,7 +265,6 @@ void rs_server::retire_step(Step &s) {
         finish(r, err == RS_OK ? DONE : FAILED, err);
     }
     (void)hipEventDestroy(s.ev_start);
-    (void)hipEventDestroy(s.ev_end);
 }
 
 void rs_server::run() {
@@ -276,13 +312,14 @@ void rs_server::run() {
         for (uint64_t t : admitted) {
             Request &r = reqs.at(t);
             r.state = ACTIVE;
-            hipError_t e = hipSuccess;
-            if (r.has_lens)
+            hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(pool + r.off_map), r.p.npx * r.p.npy, admit);
+            if (e == hipSuccess && r.has_lens)
                 e = hipMemcpyAsync(pool + r.off_lens, r.lens_xy.data(), 16 * (size_t)r.n_lens, hipMemcpyHostToDevice,
-                                   compute);
+                                   admit);
             if (e == hipSuccess && r.has_m)
                 e = hipMemcpyAsync(pool + r.off_m, r.lens_m.data(), 8 * (size_t)r.n_lens, hipMemcpyHostToDevice,
-                                   compute);
+                                   admit);
+            admit_pending = true;
             if (e != hipSuccess) {
                 policy.cancel(t);
                 r.error = RS_EHIP;
@@ -338,8 +375,11 @@ int rs_server_create(const rs_server_cfg *cfg, rs_server **out) {
         delete s;
         return fail(RS_ENOMEM, "cannot allocate a %zu-byte device pool", cfg->hbm_budget_bytes);
     }
-    if (hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&s->step_stream[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->step_stream[1], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->admit, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->admitted_ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipFree(s->pool);
         delete s;
         return fail(RS_EHIP, "cannot create streams");
@@ -461,13 +501,15 @@ void rs_server_destroy(rs_server *s) {
     }
     s->cv_work.notify_all();
     if (s->thread.joinable()) s->thread.join();
-    (void)hipStreamSynchronize(s->compute);
-    (void)hipStreamSynchronize(s->copy);
+    for (hipStream_t st : {s->step_stream[0], s->step_stream[1], s->admit, s->copy})
+        if (st) (void)hipStreamSynchronize(st);
     for (void *w : s->ws)
         if (w) (void)hipFree(w);
     (void)hipFree(s->pool);
-    (void)hipStreamDestroy(s->compute);
-    (void)hipStreamDestroy(s->copy);
+    for (hipStream_t st : {s->step_stream[0], s->step_stream[1], s->admit, s->copy})
+        if (st) (void)hipStreamDestroy(st);
+    if (s->admitted_ev) (void)hipEventDestroy(s->admitted_ev);
+    for (auto &r : s->recent) (void)hipEventDestroy(r.ev);
     delete s;
 }
 

@@ -441,6 +441,15 @@ __global__ void fill_kernel(uint32_t *map, int64_t n_pix, uint32_t *ws_words, in
 
 }  // namespace
 
+hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, stream, p, n, static_cast<uint32_t *>(nullptr),
+                       (int64_t)0);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_qcount,
                        hipStream_t stream) {
     const int64_t n_ws_words = (int64_t)(WS_QCOUNT / 4) + n_qcount;

@@ -65,33 +65,26 @@ int main() {
         put("slots_admit", list(p.admit(0.0, fits, nullptr)));
         put("slots_waiting", std::to_string(p.waiting()));
     }
-    // 3. fair slicing: equal shares, 32-row quanta, completion after all rows
+    // 3. slicing: least remaining work first, 32-row quanta, one band minimum per job
     {
         Policy p(1 << 30, 8);
-        p.submit(job(1, 1, 1000, 1000, 100));   // 1e5 interactions per row
-        p.submit(job(2, 1, 1000, 70, 100));
+        p.submit(job(1, 1, 1000, 1000, 100));   // 1e5 interactions per row, 1e8 in all
+        p.submit(job(2, 1, 1000, 70, 100));     // 7e6 in all: the smaller one
         auto fits = [](Job &) { return true; };
         p.admit(0.0, fits, nullptr);
-        std::vector<Slice> s = p.plan(2 * 64 * 1e5);  // 64 rows each
+        std::vector<Slice> s = p.plan(128 * 1e5);  // budget of 128 rows
         std::string sl = "[";
         for (size_t i = 0; i < s.size(); ++i)
             sl += (i ? "," : "") + std::string("[") + std::to_string(s[i].ticket) + "," + std::to_string(s[i].row0) +
                   "," + std::to_string(s[i].row1) + "," + (s[i].first ? "1" : "0") + "]";
-        put("fair_step1", sl + "]");
+        put("srpt_step1", sl + "]");
         std::vector<Job> d1 = p.step_done(s, 1.0);
         std::vector<uint64_t> t1;
         for (Job &j : d1) t1.push_back(j.ticket);
-        put("fair_done1", list(t1));
-        std::vector<Slice> s2 = p.plan(2 * 64 * 1e5);
-        put("fair_step2_n", std::to_string(s2.size()));
-        put("fair_step2_first", s2.empty() ? "-1" : std::to_string(s2[0].row0));
-        std::vector<Job> d2 = p.step_done(s2, 2.0);
-        std::vector<uint64_t> t2;
-        for (Job &j : d2) t2.push_back(j.ticket);
-        put("fair_done2", list(t2));
-        int steps = 2;
-        while (p.active()) { p.step_done(p.plan(2 * 64 * 1e5), 2.0 + steps); ++steps; if (steps > 100) break; }
-        put("fair_total_steps", std::to_string(steps));
+        put("srpt_done1", list(t1));
+        int steps = 1;
+        while (p.active()) { p.step_done(p.plan(128 * 1e5), 1.0 + steps); ++steps; if (steps > 100) break; }
+        put("srpt_total_steps", std::to_string(steps));
     }
     // 4. cancellation of a waiting and of a running job
     {

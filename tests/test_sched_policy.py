@@ -34,15 +34,14 @@ def test_slot_limit(res):
     assert res["slots_admit"] == [1, 2] and res["slots_waiting"] == 3
 
 
-def test_fair_slicing(res):
-    step1 = res["fair_step1"]
-    assert [s[0] for s in step1] == [1, 2]
-    assert step1[0][1:] == [0, 64, 1] and step1[1][1:] == [0, 64, 1]
-    assert res["fair_done1"] == []
-    assert res["fair_step2_n"] == 2 and res["fair_step2_first"] == 64
-    assert res["fair_done2"] == [2]         # 70 rows: done after its second slice
-    # work-conserving: once job 2 is done, job 1 gets the whole step (128 rows)
-    assert res["fair_total_steps"] == 2 + -(-(1000 - 128) // 128)
+def test_shortest_remaining_first(res):
+    step1 = res["srpt_step1"]
+    # the small job (2: 70 rows) takes its whole remainder first; the large one still gets one band
+    assert step1[0] == [2, 0, 70, 1]
+    assert step1[1] == [1, 0, 32, 1]
+    assert res["srpt_done1"] == [2]
+    # then job 1 alone: 968 rows left at 128 per step
+    assert res["srpt_total_steps"] == 1 + -(-(1000 - 32) // 128)
 
 
 def test_cancellation(res):
