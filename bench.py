@@ -37,7 +37,7 @@ METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batch
 # HBM traffic of the deflection kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on the
 # same workload, scaled by the copy-kernel calibration factor. None until measured for the
 # current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = 1.043e9   # profiles/shoot_kernel_config2.md (mixed-mode kernel)
+TRAFFIC_BYTES_PER_LAUNCH = None
 
 
 def parse():
@@ -52,7 +52,22 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the request loop vs one-at-a-time")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-rho", type=float, default=0.8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (scales HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size: 1 GiB read + 1 GiB written per launch, three launches."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}), flush=True)
 
 
 def cpu_baseline(spec, target_s: float):
@@ -85,6 +100,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU design shards ray rows and sum-reduces the uint32 maps).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     import paper_1005_5198_amd as rs
     from paper_1005_5198_amd import workloads as w
