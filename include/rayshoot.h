@@ -289,6 +289,70 @@ int rs_server_get_stats(rs_server *server, rs_server_stats *stats);
 /* Stop admitting, drop waiting requests, finish running ones, release everything. */
 void rs_server_destroy(rs_server *server);
 
+/* ---------------------------------------------------------------------------
+ * Map statistics (Section 4, accuracy assessment; Eq. deltam; Section 2, Eq. mu).
+ *
+ * A count map N (uint32, npix pixels, any layout: every statistic here is over
+ * the set of pixels) gives the magnification mu = N / N_rays and the change in
+ * magnitude dm = -2.5 log10(mu) of each pixel; a pixel without rays has mu = 0,
+ * dm = +inf. Two maps of the same source grid are compared by
+ *   - the root-mean-square of dm_a - dm_b over the pixels with rays in both
+ *     maps (a pixel empty in either map has no finite difference and is left
+ *     out; their number is reported), and
+ *   - the two-sample Kolmogorov-Smirnov statistic D of the two dm samples (all
+ *     pixels, +inf being the largest value), with its probability
+ *     P(KS) = Q((sqrt(n_e) + 0.12 + 0.11 / sqrt(n_e)) D), n_e = npix / 2, where
+ *     Q(l) = 2 sum_{j>=1} (-1)^(j-1) exp(-2 j^2 l^2) is the Kolmogorov survival
+ *     function (Stephens' effective-size correction).
+ * The histogram of counts, divided by npix, is the map's magnification
+ * probability distribution P(mu = c / N_rays).
+ * All arithmetic is FP64; the pass over the maps is bound by HBM bandwidth.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double rms_dm;        /* RMS of dm_a - dm_b over pixels with rays in both maps; NaN if none */
+    double ks_d;          /* two-sample K-S statistic D of the dm distributions */
+    double ks_p;          /* P(KS) as above */
+    double mean_mu_a;     /* sum of map_a / (npix * n_rays_a) */
+    double mean_mu_b;
+    int64_t n_pix;
+    int64_t n_both;       /* pixels in the RMS */
+    int64_t n_zero_a;     /* pixels without rays */
+    int64_t n_zero_b;
+    uint32_t max_a;       /* largest count in each map */
+    uint32_t max_b;
+} rs_compare_result;
+
+/* N_rays of a map: rays per unit area of the regular shooting grid,
+ * (nx / sw)(ny / sh), times the area of one source pixel, (tw / npx)(th / npy)
+ * (Section 3.1). Host only. Returns NaN (and sets rs_last_error) on bad params. */
+double rs_rays_per_pixel(const rs_map_params *params);
+
+/* max_dev[0] = the largest count of map[0..npix). Enqueued on stream. */
+int rs_map_max(const uint32_t *map, int64_t npix, uint32_t *max_dev, void *stream);
+
+/* hist[c] = number of pixels with count c, for c = 0..max_count, and
+ * hist[max_count + 1] = number of pixels with a larger count. hist is a device
+ * array of max_count + 2 uint64 (overwritten). Enqueued on stream. */
+int rs_map_histogram(const uint32_t *map, int64_t npix, uint32_t max_count, uint64_t *hist, void *stream);
+
+/* dm[p] = -2.5 log10(map[p] / n_rays) in FP64 (+inf where map[p] == 0).
+ * dm is a device array of npix doubles. Enqueued on stream. */
+int rs_delta_m(const uint32_t *map, int64_t npix, double n_rays, double *dm, void *stream);
+
+/* Workspace bytes of rs_compare_maps for count bounds max_a, max_b. */
+size_t rs_compare_workspace_bytes(uint32_t max_a, uint32_t max_b);
+
+/* Compare two count maps of npix pixels each (device arrays). max_a and max_b
+ * bound the counts of each map (rs_map_max gives them); the workspace is a
+ * device buffer of at least rs_compare_workspace_bytes(max_a, max_b) bytes,
+ * 256-byte aligned. Synchronous: waits for the stream, then fills
+ * *result_host. Returns RS_EINVAL when a count exceeds its bound (result_host
+ * still gets the true maxima), RS_ENOMEM when the workspace is too small. */
+int rs_compare_maps(const uint32_t *map_a, const uint32_t *map_b, int64_t npix, double n_rays_a,
+                    double n_rays_b, uint32_t max_a, uint32_t max_b, void *workspace, size_t workspace_bytes,
+                    rs_compare_result *result_host, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

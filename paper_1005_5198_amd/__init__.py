@@ -6,13 +6,17 @@ Public entry points (loaded lazily so that importing the package, e.g. for
     make_map(params, lens_xy, lens_m=None, mode="mixed") -> torch.uint32 [npy, npx]
     ray_pixels(params, lens_xy, lens_m=None, mode="mixed") -> torch.int32 [rays in window]
     read_stats(workspace) -> dict
+    make_maps(maps) / Batch / Server      many maps: one persistent launch; a request loop
+    compare_maps(map_a, map_b, n_rays_a)  RMS of dm and the K-S test between two maps
+    delta_m / histogram / map_max         per-pixel dm, count histogram, largest count
 
 ``params`` is a dict with the fields of ``rs_map_params`` (see include/rayshoot.h);
 ``paper_1005_5198_amd.workloads.make_params`` builds one.
 """
 _API = ("make_map", "ray_pixels", "read_stats", "workspace_bytes", "new_workspace", "to_params",
         "lens_tensors", "profile_enable", "profile_read", "version", "tune", "set_shape", "tune_save",
-        "tune_load", "make_maps", "Batch", "Server")
+        "tune_load", "make_maps", "Batch", "Server", "rays_per_pixel", "map_max", "histogram", "delta_m",
+        "compare_maps", "compare_workspace_bytes")
 
 
 def __getattr__(name):

@@ -81,6 +81,17 @@ class TuneResult(ctypes.Structure):
                 ("ms", ctypes.c_double * 8), ("sample_interactions", ctypes.c_double)]
 
 
+class CompareResult(ctypes.Structure):
+    _fields_ = [("rms_dm", ctypes.c_double), ("ks_d", ctypes.c_double), ("ks_p", ctypes.c_double),
+                ("mean_mu_a", ctypes.c_double), ("mean_mu_b", ctypes.c_double),
+                ("n_pix", ctypes.c_int64), ("n_both", ctypes.c_int64),
+                ("n_zero_a", ctypes.c_int64), ("n_zero_b", ctypes.c_int64),
+                ("max_a", ctypes.c_uint32), ("max_b", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 VP = ctypes.c_void_p
@@ -114,6 +125,13 @@ def _declare(lib):
         "rs_server_cancel": ([VP, ctypes.c_uint64], INT),
         "rs_server_get_stats": ([VP, P(ServerStats)], INT),
         "rs_server_destroy": ([VP], None),
+        "rs_rays_per_pixel": ([P(MapParams)], ctypes.c_double),
+        "rs_map_max": ([VP, I64, VP, VP], INT),
+        "rs_map_histogram": ([VP, I64, ctypes.c_uint32, VP, VP], INT),
+        "rs_delta_m": ([VP, I64, ctypes.c_double, VP, VP], INT),
+        "rs_compare_workspace_bytes": ([ctypes.c_uint32, ctypes.c_uint32], SZ),
+        "rs_compare_maps": ([VP, VP, I64, ctypes.c_double, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
+                             VP, SZ, P(CompareResult), VP], INT),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -145,4 +163,5 @@ def exported_symbols():
             "rs_read_stats", "rs_profile_enable", "rs_profile_read", "rs_tune", "rs_set_shape",
             "rs_tune_save", "rs_tune_load", "rs_batch_workspace_bytes", "rs_make_maps",
             "rs_batch_read_stats", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
-            "rs_server_cancel", "rs_server_get_stats", "rs_server_destroy"]
+            "rs_server_cancel", "rs_server_get_stats", "rs_server_destroy", "rs_rays_per_pixel", "rs_map_max",
+            "rs_map_histogram", "rs_delta_m", "rs_compare_workspace_bytes", "rs_compare_maps"]

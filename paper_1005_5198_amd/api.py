@@ -286,3 +286,84 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Map statistics (Section 4, accuracy assessment; Eq. deltam): dm per pixel,
+# count histograms, and the RMS / K-S comparison of two maps.
+# ---------------------------------------------------------------------------
+
+def _count_map(t, name="map") -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous uint32 device tensor")
+    if t.numel() < 1:
+        raise ValueError(f"{name} is empty")
+    return t
+
+
+def rays_per_pixel(params: dict) -> float:
+    """N_rays of the params' shooting and source grids (Section 3.1)."""
+    c = to_params(params, "fp32")
+    v = float(L.lib().rs_rays_per_pixel(ctypes.byref(c)))
+    if v != v:
+        L.check(L.RS_EINVAL)
+    return v
+
+
+def map_max(counts: torch.Tensor, stream=None, out: Optional[torch.Tensor] = None):
+    """Largest count of a map. With ``out`` (a 1-element int32 device tensor, read as uint32)
+    the call is asynchronous and returns ``out``; otherwise it returns a Python int."""
+    _count_map(counts)
+    dst = out if out is not None else torch.empty(1, dtype=torch.int32, device=counts.device)
+    L.check(L.lib().rs_map_max(counts.data_ptr(), counts.numel(), dst.data_ptr(), _stream_handle(stream)))
+    if out is not None:
+        return out
+    return int(dst.item()) & 0xFFFFFFFF
+
+
+def histogram(counts: torch.Tensor, max_count: Optional[int] = None, stream=None) -> torch.Tensor:
+    """int64 device tensor [max_count + 2]: pixels per count 0..max_count, then pixels above."""
+    _count_map(counts)
+    if max_count is None:
+        max_count = map_max(counts, stream)
+    hist = torch.empty(int(max_count) + 2, dtype=torch.int64, device=counts.device)
+    L.check(L.lib().rs_map_histogram(counts.data_ptr(), counts.numel(), int(max_count), hist.data_ptr(),
+                                     _stream_handle(stream)))
+    return hist
+
+
+def delta_m(counts: torch.Tensor, n_rays: float, stream=None) -> torch.Tensor:
+    """float64 device tensor of dm = -2.5 log10(N / N_rays), the map's shape (+inf where N = 0)."""
+    _count_map(counts)
+    dm = torch.empty(counts.shape, dtype=torch.float64, device=counts.device)
+    L.check(L.lib().rs_delta_m(counts.data_ptr(), counts.numel(), float(n_rays), dm.data_ptr(),
+                               _stream_handle(stream)))
+    return dm
+
+
+def compare_workspace_bytes(max_a: int, max_b: int) -> int:
+    """Workspace bytes of compare_maps for count bounds max_a, max_b."""
+    return int(L.lib().rs_compare_workspace_bytes(int(max_a), int(max_b)))
+
+
+def compare_maps(map_a: torch.Tensor, map_b: torch.Tensor, n_rays_a: float, n_rays_b: Optional[float] = None,
+                 max_a: Optional[int] = None, max_b: Optional[int] = None,
+                 workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
+    """RMS of dm_a - dm_b, K-S statistic D and P(KS), mean magnifications, empty pixels."""
+    _count_map(map_a, "map_a")
+    _count_map(map_b, "map_b")
+    if map_a.numel() != map_b.numel():
+        raise ValueError("maps differ in size")
+    n_rays_b = n_rays_a if n_rays_b is None else n_rays_b
+    if max_a is None:
+        max_a = map_max(map_a, stream)
+    if max_b is None:
+        max_b = map_max(map_b, stream)
+    need = compare_workspace_bytes(max_a, max_b)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=map_a.device)
+    res = L.CompareResult()
+    L.check(L.lib().rs_compare_maps(map_a.data_ptr(), map_b.data_ptr(), map_a.numel(), float(n_rays_a),
+                                    float(n_rays_b), int(max_a), int(max_b), workspace.data_ptr(),
+                                    workspace.numel(), ctypes.byref(res), _stream_handle(stream)))
+    return res.as_dict()

@@ -123,3 +123,43 @@ def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed
             "served_max_waiting": st["max_waiting"], "served_hbm_peak_bytes": st["hbm_peak_bytes"],
             "plain_maps_per_s": n_requests / span_plain, "plain_p50_s": p50p, "plain_p99_s": p99p,
             "plain_span_s": span_plain, "identical_first8": identical}
+
+
+def map_stats(rs, side: int = 4096, n_rays_a: float = 500.0, n_rays_b: float = 1000.0, reps: int = 20) -> dict:
+    """Comparison of two side^2 count maps (the accuracy assessment's largest map size).
+
+    Reports the whole rs_compare_maps call (five launches, the result read back),
+    the histogram and dm calls, each averaged over reps after one warm-up, and
+    the HBM rate of the comparison counted as the 8 bytes per pixel pair its
+    pass reads."""
+    a, b = w.count_map_pair(side, side, n_rays_a, n_rays_b, seed=16, spike_frac=2e-4)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    ma, mb = rs.map_max(da), rs.map_max(db)
+    ws = torch.empty(int(rs.compare_workspace_bytes(ma, mb)), dtype=torch.uint8, device="cuda")
+    res = rs.compare_maps(da, db, n_rays_a, n_rays_b, ma, mb, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        res = rs.compare_maps(da, db, n_rays_a, n_rays_b, ma, mb, workspace=ws)
+    dt_cmp = (time.perf_counter() - t) / reps
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_hist = timed(lambda: rs.histogram(da, ma))
+    ms_dm = timed(lambda: rs.delta_m(da, n_rays_a))
+    ms_max = timed(lambda: rs.map_max(da, out=torch.empty(1, dtype=torch.int32, device="cuda")))
+    npix = side * side
+    return {"pixels": npix, "max_counts": [ma, mb], "compare_ms": dt_cmp * 1e3,
+            "compare_pass_bytes": 8 * npix, "compare_GBps_wall": 8 * npix / dt_cmp / 1e9,
+            "histogram_ms": ms_hist, "delta_m_ms": ms_dm, "map_max_ms": ms_max,
+            "delta_m_GBps": 12 * npix / (ms_dm * 1e-3) / 1e9,
+            "rms_dm": res["rms_dm"], "ks_d": res["ks_d"], "ks_p": res["ks_p"]}

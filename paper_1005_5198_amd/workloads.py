@@ -216,3 +216,22 @@ def paper_point(sigma: float, gamma: float, sigma_c: float = 0.0, n_pix_side: in
 
 
 CONFIGS = {"c0": config0, "c1": config1, "c2": config2}
+
+
+def count_map_pair(ny: int, nx: int, n_rays_a: float, n_rays_b: float, seed: int,
+                   spike_frac: float = 1e-3, spike_mu=(50.0, 3000.0), log_sigma: float = 0.6):
+    """Two uint32 count maps of one synthetic magnification field, as two codes would make them.
+
+    The field: log-normal magnifications (median 1, ln-spread log_sigma) with a
+    fraction spike_frac of pixels near caustics (mu log-uniform in spike_mu).
+    Each map draws its counts independently, Poisson(mu * N_rays), so low N_rays
+    leaves empty pixels and the spikes reach counts far above the median.
+    """
+    rng = np.random.default_rng(seed)
+    mu = rng.lognormal(0.0, log_sigma, size=(ny, nx))
+    spikes = rng.random((ny, nx)) < spike_frac
+    lo, hi = math.log(spike_mu[0]), math.log(spike_mu[1])
+    mu[spikes] = np.exp(rng.uniform(lo, hi, size=int(spikes.sum())))
+    a = rng.poisson(mu * n_rays_a).astype(np.uint32)
+    b = rng.poisson(mu * n_rays_b).astype(np.uint32)
+    return a, b

@@ -1,6 +1,7 @@
 """The C-ABI library on the CPU: it loads, exports every declared symbol, and
 validates arguments before touching a device. No compute calls (no GPU here)."""
 import ctypes
+import math
 import os
 import re
 
@@ -102,3 +103,28 @@ def test_set_shape_range(lib):
         api.set_shape(99)
     prev = api.set_shape(2)
     assert api.set_shape(prev) == 2
+
+
+def test_map_statistics_validation(lib):
+    """Argument checks of the map-statistics entry points (nothing reaches a device)."""
+    from paper_1005_5198_amd import _lib as L, api, workloads as w
+    s = w.config0()
+    assert api.rays_per_pixel(s.params) == pytest.approx(4.0, rel=1e-15)
+    bad = dict(s.params)
+    bad["sw"] = -1.0
+    assert math.isnan(lib.rs_rays_per_pixel(ctypes.byref(api.to_params(bad))))
+    small = lib.rs_compare_workspace_bytes(10, 20)
+    assert small >= 256 + 64 * 1024 + 8 * (12 + 22)
+    up = lambda v: (v + 255) // 256 * 256   # histograms of max + 2 uint64, 256-byte aligned
+    assert lib.rs_compare_workspace_bytes(1000, 20) - small == up(8 * 1002) - up(8 * 12)
+    res = L.CompareResult()
+    fake = 1 << 20   # never dereferenced: validation fails first
+    assert lib.rs_compare_maps(None, fake, 16, 1.0, 1.0, 4, 4, fake, 1 << 20, ctypes.byref(res), None) == L.RS_EINVAL
+    assert b"map_a" in lib.rs_last_error()
+    assert lib.rs_compare_maps(fake, fake, 0, 1.0, 1.0, 4, 4, fake, 1 << 20, ctypes.byref(res), None) == L.RS_EINVAL
+    assert lib.rs_compare_maps(fake, fake, 16, 0.0, 1.0, 4, 4, fake, 1 << 20, ctypes.byref(res), None) == L.RS_EINVAL
+    assert lib.rs_compare_maps(fake, fake, 16, 1.0, 1.0, 4, 4, fake, 100, ctypes.byref(res), None) == L.RS_ENOMEM
+    assert lib.rs_compare_maps(fake, fake, 16, 1.0, 1.0, 4, 4, fake + 8, 1 << 20, ctypes.byref(res), None) == L.RS_EINVAL
+    assert lib.rs_map_histogram(fake, 16, 0xFFFFFFFF, fake, None) == L.RS_EINVAL
+    assert lib.rs_delta_m(fake, 16, float("nan"), fake, None) == L.RS_EINVAL
+    assert lib.rs_map_max(fake + 2, 16, fake, None) == L.RS_EINVAL
