@@ -34,7 +34,8 @@ class OracleParams(ctypes.Structure):
                 ("j0", ctypes.c_int64), ("j1", ctypes.c_int64),
                 ("tx0", ctypes.c_double), ("ty0", ctypes.c_double),
                 ("tw", ctypes.c_double), ("th", ctypes.c_double),
-                ("npx", ctypes.c_int64), ("npy", ctypes.c_int64)]
+                ("npx", ctypes.c_int64), ("npy", ctypes.c_int64),
+                ("random_rays", ctypes.c_int64), ("seed", ctypes.c_uint64)]
 
 
 def build(force: bool = True, extra_flags=(), src: str = SRC, out: str = LIB) -> str:
@@ -61,6 +62,8 @@ class _Lib:
         lib.oracle_ray_pixels.argtypes = [P(OracleParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.oracle_ray_pixels.restype = ctypes.c_int
+        lib.oracle_philox4x64.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_philox4x64.restype = None
         self.lib = lib
         self.path = path
 
@@ -69,6 +72,9 @@ class _Lib:
 
     def ray_pixels(self, params, lens_xy, lens_m=None, nthreads=None):
         return ray_pixels(params, lens_xy, lens_m, nthreads, _use=self.lib)
+
+    def philox4x64(self, counter, key):
+        return philox4x64(counter, key, _use=self.lib)
 
 
 _default = None
@@ -94,7 +100,8 @@ def default() -> _Lib:
 
 
 def _params(p: dict) -> OracleParams:
-    return OracleParams(*(p[k] for k, _ in OracleParams._fields_))
+    """Missing random_rays / seed mean the regular grid."""
+    return OracleParams(*(p.get(k, 0) if k in ("random_rays", "seed") else p[k] for k, _ in OracleParams._fields_))
 
 
 def _lens(lens_xy, lens_m):
@@ -128,6 +135,16 @@ def make_map(params: dict, lens_xy, lens_m=None, near_tol: float = 1e-9, near_ca
     stats = dict(rays_in_map=int(counts[0]), rays_out=int(counts[1]), rays_singular=int(counts[2]),
                  near_edge=n_near, near_edge_rays=[tuple(r) for r in near[:min(n_near, near_cap)]])
     return out, stats
+
+
+def philox4x64(counter, key, _use=None):
+    """Philox4x64-10 block (four uint64) of counter (4 words) under key (2 words)."""
+    lib = _use or _load()
+    c = np.ascontiguousarray(np.asarray(counter, dtype=np.uint64).reshape(4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64).reshape(2))
+    out = np.zeros(4, dtype=np.uint64)
+    lib.oracle_philox4x64(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
 
 
 def ray_pixels(params: dict, lens_xy, lens_m=None, nthreads: Optional[int] = None, _use=None):

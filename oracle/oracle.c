@@ -16,6 +16,13 @@
  *   - Section 3.1: rays are shot on a regular grid (CPU-T/CPU-P), so that with
  *     no lensing every pixel receives exactly N_rays rays. Rays are placed at
  *     cell centres, x1 = sx0 + (i + 1/2) sw/nx.
+ *   - Section 3.1 (the GPU code's sampling): alternatively every ray sits at an
+ *     independent uniformly random position in the shooting rectangle, so a
+ *     pixel receives N_rays rays only on average, with Poisson noise. Ray (i, j)
+ *     takes its two uniforms from the counter-based generator Philox4x64-10
+ *     (Salmon, Moraes, Dror & Shaw 2011) at counter (j nx + i, 0, 0, 0) and key
+ *     (seed, 0): U = (top 52 bits of a 64-bit output + 1/2) 2^-52, strictly
+ *     inside (0, 1); x1 = sx0 + U1 sw, x2 = sy0 + U2 sh.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - the sum runs over lenses in index order k = 0..N*-1, sequentially, with
@@ -43,6 +50,8 @@ typedef struct {
     int64_t i0, i1, j0, j1;
     double tx0, ty0, tw, th;
     int64_t npx, npy;
+    int64_t random_rays;   /* 0: regular grid; 1: Philox-random positions */
+    uint64_t seed;
 } oracle_params;
 
 enum { RAY_OUT = -1, RAY_SINGULAR = -2 };
@@ -53,13 +62,59 @@ typedef struct {
     int64_t pix;     /* v*npx + u, RAY_OUT or RAY_SINGULAR */
 } ray_result;
 
+/* Philox4x64-10: ten rounds of two 64x64->128-bit products, the key bumped by
+ * the Weyl constants between rounds. */
+void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        const unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Image-plane position of ray (i, j). */
+static void ray_position(const oracle_params *p, int64_t i, int64_t j, double *x1, double *x2)
+{
+    if (p->random_rays) {
+        const uint64_t ctr[4] = {(uint64_t)j * (uint64_t)p->nx + (uint64_t)i, 0, 0, 0};
+        const uint64_t key[2] = {p->seed, 0};
+        uint64_t out[4];
+        oracle_philox4x64(ctr, key, out);
+        const double u1 = ((double)(out[0] >> 12) + 0.5) * 0x1p-52;
+        const double u2 = ((double)(out[1] >> 12) + 0.5) * 0x1p-52;
+        *x1 = p->sx0 + u1 * p->sw;
+        *x2 = p->sy0 + u2 * p->sh;
+    } else {
+        /* Section 3.1: regular grid, cell-centred. */
+        *x1 = p->sx0 + ((double)i + 0.5) * (p->sw / (double)p->nx);
+        *x2 = p->sy0 + ((double)j + 0.5) * (p->sh / (double)p->ny);
+    }
+}
+
 static ray_result shoot_one(const oracle_params *p, const double *lens_xy, const double *lens_m,
                             int64_t n_lens, int64_t i, int64_t j)
 {
     ray_result r;
-    /* Section 3.1: regular grid, cell-centred. */
-    const double x1 = p->sx0 + ((double)i + 0.5) * (p->sw / (double)p->nx);
-    const double x2 = p->sy0 + ((double)j + 0.5) * (p->sh / (double)p->ny);
+    double x1, x2;
+    ray_position(p, i, j, &x1, &x2);
 
     /* Eq. (sigma), the point-mass sum, in lens order. */
     double a1 = 0.0, a2 = 0.0;

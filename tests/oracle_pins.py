@@ -229,7 +229,100 @@ def pin_singular(orc):
     assert pix[5 * 16 + 5] == -2
 
 
+# ---------------------------------------------------------------------------
+# Random rays (the GPU code's sampling, Section 3.1): Philox4x64-10 against
+# numpy's independent implementation, and the statistics the sampling fixes.
+# ---------------------------------------------------------------------------
+def _numpy_philox(counter, key):
+    """numpy's Philox advances its counter before each block, so start one below."""
+    c = [int(x) for x in counter]
+    k = 0
+    while c[k] == 0 and k < 3:
+        c[k] = (1 << 64) - 1
+        k += 1
+    c[k] = (c[k] - 1) % (1 << 64)
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    return [int(x) for x in bg.random_raw(4)]
+
+
+def pin_philox(orc, seed=21):
+    rng = np.random.default_rng(seed)
+    cases = [([0, 0, 0, 0], [0, 0]), ([(1 << 64) - 1] * 4, [(1 << 64) - 1] * 2)]
+    for _ in range(12):
+        cases.append(([int(x) for x in rng.integers(0, 1 << 63, 4, dtype=np.uint64)],
+                      [int(x) for x in rng.integers(0, 1 << 63, 2, dtype=np.uint64)]))
+    for ctr, key in cases:
+        got = [int(x) for x in orc.philox4x64(ctr, key)]
+        assert got == _numpy_philox(ctr, key), f"philox block differs at counter {ctr} key {key}"
+
+
+def _random(p, seed):
+    q = dict(p)
+    q.update(random_rays=1, seed=seed)
+    return q
+
+
+def pin_random_identity(orc):
+    """Identity lensing with random rays: every ray lands in the map (positions strictly inside
+    the rectangle), the total is exactly the regular grid's, and the per-pixel counts scatter
+    like a multinomial draw (chi-square dispersion), where the regular grid has none."""
+    from scipy import stats
+    shoot, src = (-6.0, -3.0, 12.0, 6.0, 240, 120), (-6.0, -3.0, 12.0, 6.0, 48, 24)
+    p = _p(0.0, 0.0, shoot, src)
+    grid, _ = orc.make_map(p, NO_LENS)
+    assert np.all(grid == 25)
+    rnd, st = orc.make_map(_random(p, 7), NO_LENS)
+    assert st["rays_out"] == 0 and int(rnd.sum()) == 240 * 120
+    chi2 = float(((rnd.astype(np.float64) - 25.0) ** 2).sum() / 25.0)
+    dof = rnd.size - 1
+    pval = stats.chi2.sf(chi2, dof)
+    assert 1e-4 < pval < 1 - 1e-4, f"random-ray counts not multinomial: chi2 {chi2:.1f} on {dof} dof"
+    # positions are uniform along each axis (Kolmogorov-Smirnov against U(0,1))
+    pix, u, v = orc.ray_pixels(_random(p, 7), NO_LENS)
+    assert stats.kstest(u / 48.0, "uniform").pvalue > 1e-4
+    assert stats.kstest(v / 24.0, "uniform").pvalue > 1e-4
+    # another seed is another drawing, the same seed the same one
+    again, _ = orc.make_map(_random(p, 7), NO_LENS)
+    other, _ = orc.make_map(_random(p, 8), NO_LENS)
+    assert np.array_equal(again, rnd) and not np.array_equal(other, rnd)
+
+
+def pin_random_wiring(orc):
+    """Ray (i, j) takes its uniforms from the block at counter (j nx + i, 0, 0, 0), key (seed, 0):
+    under identity lensing u is the ray's first uniform in pixel units (to rounding)."""
+    shoot = (-6.0, -3.0, 12.0, 6.0, 240, 120)
+    p = _random(_p(0.0, 0.0, shoot, shoot[:4] + (48, 24), window=(17, 20, 33, 35)), 99)
+    pix, u, v = orc.ray_pixels(p, NO_LENS)
+    for n, (i, j) in enumerate((i, j) for j in range(33, 35) for i in range(17, 20)):
+        out = _numpy_philox([j * 240 + i, 0, 0, 0], [99, 0])
+        u1 = ((out[0] >> 12) + 0.5) / 2.0 ** 52
+        u2 = ((out[1] >> 12) + 0.5) / 2.0 ** 52
+        assert abs(u[n] - 48.0 * u1) < 1e-9 and abs(v[n] - 24.0 * u2) < 1e-9, (i, j)
+
+
+def pin_random_mean_mu(orc):
+    """Pure convergence and shear with random rays: rays uniform over the shooting rectangle map
+    onto a uniform density |mu_av| times the unlensed one, so the mean count per pixel is
+    |mu_av| N_rays up to multinomial noise (five standard deviations)."""
+    sigma_c, gamma = 0.25, 0.15
+    a1, a2 = 1 - gamma - sigma_c, 1 + gamma - sigma_c
+    src = (-4.0, -4.0, 8.0, 8.0, 32, 32)
+    # shooting rectangle = preimage of a source square of side 10 (covers the map with margin)
+    shoot = (-5.0 / a1, -5.0 / a2, 10.0 / a1, 10.0 / a2, 400, 400)
+    p = _random(_p(sigma_c, gamma, shoot, src), 5)
+    m, st = orc.make_map(p, NO_LENS)
+    frac = (8.0 * 8.0) / (10.0 * 10.0)      # share of the rays whose image lands in the map
+    n = 400 * 400
+    expect = n * frac
+    assert abs(int(m.sum()) - expect) < 5 * math.sqrt(n * frac * (1 - frac))
+    assert st["rays_in_map"] + st["rays_out"] == n
+
+
 ALL_PINS = {
+    "philox": pin_philox,
+    "random_identity": pin_random_identity,
+    "random_wiring": pin_random_wiring,
+    "random_mean_mu": pin_random_mean_mu,
     "identity": pin_identity,
     "separable": pin_separable,
     "mean_mu": pin_mean_mu,

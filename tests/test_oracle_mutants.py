@@ -1,6 +1,6 @@
 """Pin sensitivity: plausible mistakes planted in copies of the oracle must fail a pin.
 
-Each mutant is a one-line textual change to a temporary copy of oracle.c,
+Each mutant (15 on the lens equation and the grid, 7 on the random rays) is a one-line textual change to a temporary copy of oracle.c,
 compiled on the CPU into a temporary library. The committed oracle is never
 modified. The unmutated source must pass every pin (test_oracle_pins.py).
 """
@@ -21,8 +21,8 @@ MUTANTS = {
     "dropped_y_term_in_r2": ("const double r2 = d1 * d1 + d2 * d2;", "const double r2 = d1 * d1 + d1 * d1;"),
     "wrong_lens_index": ("const double d2 = x2 - lens_xy[2 * k + 1];", "const double d2 = x2 - lens_xy[2 * k];"),
     "mass_ignored": ("const double m = lens_m ? lens_m[k] : 1.0;", "const double m = 1.0;"),
-    "corner_rays": ("const double x1 = p->sx0 + ((double)i + 0.5) * (p->sw / (double)p->nx);",
-                    "const double x1 = p->sx0 + ((double)i) * (p->sw / (double)p->nx);"),
+    "corner_rays": ("*x1 = p->sx0 + ((double)i + 0.5) * (p->sw / (double)p->nx);",
+                    "*x1 = p->sx0 + ((double)i) * (p->sw / (double)p->nx);"),
     "spacing_uses_ny": ("(p->sw / (double)p->nx)", "(p->sw / (double)p->ny)"),
     "pixel_size_uses_npx": ("r.v = (y2 - p->ty0) / (p->th / (double)p->npy);",
                             "r.v = (y2 - p->ty0) / (p->th / (double)p->npx);"),
@@ -33,6 +33,15 @@ MUTANTS = {
     "singular_counted_as_out": ("r.pix = RAY_SINGULAR;\n            return r;",
                                 "r.pix = RAY_OUT;\n            return r;"),
     "macro_term_dropped": ("const double y2 = c2 * x2 - a2;", "const double y2 = x2 - a2;"),
+    "philox_multiplier": ("M0 = 0xD2E7470EE14C6C93ull", "M0 = 0xD2E7470EE14C6C95ull"),
+    "philox_key_not_bumped": ("k1 += W1;", "k1 += 0;"),
+    "philox_output_words": ("c2 = hi0 ^ c3 ^ k1;", "c2 = hi0 ^ c1 ^ k1;"),
+    "uniform_53_bits": ("const double u1 = ((double)(out[0] >> 12) + 0.5) * 0x1p-52;",
+                        "const double u1 = ((double)(out[0] >> 11) + 0.5) * 0x1p-52;"),
+    "uniform_axis_extent": ("*x2 = p->sy0 + u2 * p->sh;", "*x2 = p->sy0 + u2 * p->sw;"),
+    "uniform_reused": ("const double u2 = ((double)(out[1] >> 12) + 0.5) * 0x1p-52;",
+                       "const double u2 = ((double)(out[0] >> 12) + 0.5) * 0x1p-52;"),
+    "counter_transposed": ("(uint64_t)j * (uint64_t)p->nx + (uint64_t)i", "(uint64_t)i * (uint64_t)p->ny + (uint64_t)j"),
 }
 
 
