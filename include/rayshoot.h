@@ -12,6 +12,14 @@
  *     reach each source pixel; mu_ij = N_ij / N_rays.
  *   - Section 3.1: rays sit on a regular image-plane grid. Here ray (i, j) is
  *     at the cell centre x1 = sx0 + (i + 1/2) sw/nx, x2 = sy0 + (j + 1/2) sh/ny.
+ *   - Section 3.1, the GPU code's sampling (flag RS_RANDOM_RAYS): ray (i, j)
+ *     instead sits at an independent uniformly random point of the shooting
+ *     rectangle, x1 = sx0 + U1 sw, x2 = sy0 + U2 sh, so a pixel receives N_rays
+ *     only on average (Poisson noise). U1, U2 come from the counter-based
+ *     generator Philox4x64-10 (Salmon et al. 2011) at counter (j nx + i, 0, 0, 0)
+ *     and key (seed, 0): U = (output word >> 12, plus 1/2) * 2^-52, words 0
+ *     and 1 of the block. A ray's position depends only on (i, j) and the seed,
+ *     so windows of one map still sum to the whole map.
  *   - Pixel (p, q) of the source map covers u in [p, p+1), v in [q, q+1), with
  *     u = (y1 - tx0) / (tw/npx) and v = (y2 - ty0) / (th/npy). Rays outside
  *     [0,npx) x [0,npy), or with a non-finite position, are counted as "out".
@@ -64,6 +72,8 @@ extern "C" {
 #define RS_ACCUMULATE 1      /* flag: add to the map instead of zeroing it first */
 #define RS_EXACT_RECHECK 2   /* flag (RS_MIXED): re-check every queued ray with the definition's exact
                                 FP64 sequence only, skipping the faster bounded FP64 first stage */
+#define RS_RANDOM_RAYS 4     /* flag: Philox-random ray positions instead of the regular grid
+                                (rs_make_map and rs_ray_pixels; not in batches or the server) */
 
 /* One map: macro model, shooting grid, ray window and source grid. */
 typedef struct {
@@ -78,7 +88,8 @@ typedef struct {
     double tw, th;          /* source map width and height, > 0 */
     int64_t npx, npy;       /* source pixels, > 0; the map is uint32 [npy][npx] row-major */
     int32_t mode;           /* RS_FP32 or RS_MIXED */
-    int32_t flags;          /* 0 or an OR of RS_ACCUMULATE, RS_EXACT_RECHECK */
+    int32_t flags;          /* 0 or an OR of RS_ACCUMULATE, RS_EXACT_RECHECK, RS_RANDOM_RAYS */
+    uint64_t seed;          /* RS_RANDOM_RAYS: the generator key's first word */
 } rs_map_params;
 
 /* Counters of one map (or window), accumulated on the device. */
@@ -230,7 +241,8 @@ int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_ho
 /* their device footprint (lenses, masses, map) fits the server's pool, and    */
 /* keeps two launch steps in flight. Each step hands out about slice_ms of GPU  */
 /* work as bands of ray rows, least remaining work first (every active request */
-/* gets at least one 32-row band), and runs them as one rs_make_maps batch. A  */
+/* gets at least one 32-row band; one waiting longer than starve_s since its   */
+/* submission goes first), and runs them as one rs_make_maps batch. A          */
 /* request that arrives while the GPU is busy joins the next step; a small one */
 /* then finishes without waiting for large ones. Each finished map equals      */
 /* rs_make_map of the same request bit for bit (a map is the integer sum of its */
@@ -242,6 +254,7 @@ typedef struct {
     int32_t max_inflight;     /* requests admitted at once (slots), >= 1 */
     int32_t mode;             /* RS_FP32 or RS_MIXED, for every request */
     double slice_ms;          /* target GPU time of one launch step; <= 0 selects 10 ms */
+    double starve_s;          /* a request older than this is served first; <= 0 selects 0.5 s */
 } rs_server_cfg;
 
 typedef struct {

@@ -21,6 +21,7 @@ RS_FP32 = 0
 RS_MIXED = 1
 RS_ACCUMULATE = 1
 RS_EXACT_RECHECK = 2
+RS_RANDOM_RAYS = 4
 
 _ERRNAMES = {RS_EINVAL: "RS_EINVAL", RS_ENOMEM: "RS_ENOMEM", RS_EHIP: "RS_EHIP",
              RS_EBUSY: "RS_EBUSY", RS_ECANCELED: "RS_ECANCELED"}
@@ -42,7 +43,7 @@ class MapParams(ctypes.Structure):
                 ("tx0", ctypes.c_double), ("ty0", ctypes.c_double),
                 ("tw", ctypes.c_double), ("th", ctypes.c_double),
                 ("npx", ctypes.c_int64), ("npy", ctypes.c_int64),
-                ("mode", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("flags", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class MapStats(ctypes.Structure):
@@ -61,7 +62,7 @@ class MapRequest(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("slice_ms", ctypes.c_double)]
+                ("mode", ctypes.c_int32), ("slice_ms", ctypes.c_double), ("starve_s", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):

@@ -18,7 +18,9 @@ MODES = {"fp32": L.RS_FP32, "mixed": L.RS_MIXED}
 
 
 def to_params(p: dict, mode: str = "mixed", accumulate: bool = False, exact_recheck: bool = False) -> L.MapParams:
-    """Build the C parameter struct from a workloads-style dict (keys of MapParams)."""
+    """Build the C parameter struct from a workloads-style dict (keys of MapParams).
+
+    Optional keys: ``random_rays`` (true: Philox-random ray positions) and ``seed``."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {sorted(MODES)}")
     s = L.MapParams()
@@ -26,7 +28,10 @@ def to_params(p: dict, mode: str = "mixed", accumulate: bool = False, exact_rech
         if name == "mode":
             s.mode = MODES[mode]
         elif name == "flags":
-            s.flags = (L.RS_ACCUMULATE if accumulate else 0) | (L.RS_EXACT_RECHECK if exact_recheck else 0)
+            s.flags = ((L.RS_ACCUMULATE if accumulate else 0) | (L.RS_EXACT_RECHECK if exact_recheck else 0) |
+                       (L.RS_RANDOM_RAYS if p.get("random_rays") else 0))
+        elif name == "seed":
+            s.seed = int(p.get("seed", 0))
         else:
             setattr(s, name, p[name])
     return s
@@ -227,9 +232,9 @@ class Server:
     """The request loop (continuous batching). Inputs are host arrays; results come back as numpy maps."""
 
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_inflight: int = 16, mode: str = "mixed",
-                 slice_ms: float = 10.0):
+                 slice_ms: float = 10.0, starve_s: float = 0.5):
         _device()
-        cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms))
+        cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms), float(starve_s))
         h = ctypes.c_void_p()
         L.check(L.lib().rs_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

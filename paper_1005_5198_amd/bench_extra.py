@@ -62,7 +62,8 @@ def _percentiles(lat):
 
 
 def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed: int = 4,
-           budget_bytes: int = 2 << 30, max_inflight: int = 16, slice_ms: float = 10.0) -> dict:
+           budget_bytes: int = 2 << 30, max_inflight: int = 16, slice_ms: float = 10.0,
+           starve_s: float = 0.5) -> dict:
     """Poisson arrivals of config-3-distributed requests (each with its own lens set):
     the request loop vs the same arrivals served one at a time by plain rs_make_map calls."""
     import threading
@@ -96,7 +97,8 @@ def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed
 
     # the request loop
     tickets = [None] * n_requests
-    with rs.Server(hbm_budget_bytes=budget_bytes, max_inflight=max_inflight, mode=mode, slice_ms=slice_ms) as srv:
+    with rs.Server(hbm_budget_bytes=budget_bytes, max_inflight=max_inflight, mode=mode, slice_ms=slice_ms,
+                   starve_s=starve_s) as srv:
         t0 = time.perf_counter()
 
         def feed():
@@ -163,3 +165,55 @@ def map_stats(rs, side: int = 4096, n_rays_a: float = 500.0, n_rays_b: float = 1
             "histogram_ms": ms_hist, "delta_m_ms": ms_dm, "map_max_ms": ms_max,
             "delta_m_GBps": 12 * npix / (ms_dm * 1e-3) / 1e9,
             "rms_dm": res["rms_dm"], "ks_d": res["ks_d"], "ks_p": res["ks_p"]}
+
+
+def phi_fiducial(rs, rows: int = 64, full: bool = False, band_rows: int = 2400, mode: str = "mixed") -> dict:
+    """The 1e6-lens, 2500^2-pixel, 3.1e15-interaction map of Section 3.1's Phi_fiducial.
+
+    By default a band of `rows` ray rows through the middle of the map is timed
+    (3.6e12 interactions at 64 rows) and the full map's time is projected from
+    its rate; with full=True the whole map is made band by band (about 8 minutes
+    on one GPU), printing one progress line per band."""
+    import sys
+    spec = w.phi_fiducial()
+    p = spec.params
+    nx, ny = p["nx"], p["ny"]
+    xy, _ = rs.lens_tensors(spec.lens_xy)
+    if not full:
+        j0 = ny // 2 - rows // 2
+        sub = spec.window(0, nx, j0, j0 + rows)
+        ws = rs.new_workspace(sub.params, spec.n_lens, mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs.make_map(sub.params, xy, None, mode=mode, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st = rs.read_stats(ws)
+        rate = sub.interactions / dt
+        return {"workload": spec.name, "rows": rows, "rays": sub.n_rays, "lenses": spec.n_lens,
+                "interactions": sub.interactions, "seconds": dt, "rate": rate,
+                "pct_fp32_peak": 10.0 * rate / 157.3e12, "recheck_fraction": st["rays_rechecked"] / sub.n_rays,
+                "projected_full_map_s": spec.interactions / rate}
+    out = torch.zeros((p["npy"], p["npx"]), dtype=torch.uint32, device="cuda")
+    ws = None
+    total = {"rays_in_map": 0, "rays_out": 0, "rays_singular": 0, "rays_rechecked": 0}
+    t = time.perf_counter()
+    for j0 in range(0, ny, band_rows):
+        j1 = min(ny, j0 + band_rows)
+        sub = spec.window(0, nx, j0, j1)
+        if ws is None:
+            ws = rs.new_workspace(sub.params, spec.n_lens, mode)
+        rs.make_map(sub.params, xy, None, mode=mode, out=out, accumulate=True, workspace=ws)
+        st = rs.read_stats(ws)
+        for k in total:
+            total[k] += st[k]
+        print(f"phi_fiducial band rows {j0}..{j1} of {ny}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    rate = spec.interactions / dt
+    return {"workload": spec.name, "rows": ny, "rays": spec.n_rays, "lenses": spec.n_lens,
+            "interactions": spec.interactions, "seconds": dt, "rate": rate,
+            "pct_fp32_peak": 10.0 * rate / 157.3e12, "recheck_fraction": total["rays_rechecked"] / spec.n_rays,
+            "rays_in_map": total["rays_in_map"], "rays_out": total["rays_out"],
+            "map_sum": int(out.to(torch.int64).sum().item())}

@@ -36,6 +36,7 @@ namespace {
 
 constexpr int PASS_THREADS = 256;
 constexpr int LDS_BINS = 4096;          // per map
+constexpr int DM_TBL = 1536;            // per map: dm of counts below this, from an LDS table
 constexpr int MAX_PASS_BLOCKS = 1024;
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 4;
@@ -124,7 +125,7 @@ __device__ __forceinline__ void bin_count(uint32_t c, uint32_t max_c, uint32_t *
 
 template <bool PAIR>
 __device__ __forceinline__ void visit(const PassArgs &a, PassState<PAIR> &s, uint32_t ca, uint32_t cb,
-                                      uint32_t *lds_a, uint32_t *lds_b) {
+                                      uint32_t *lds_a, uint32_t *lds_b, const double *tbl) {
     bin_count(ca, a.max_a, lds_a, a.hist_a);
     s.mx_a = max(s.mx_a, ca);
     s.sum_a += ca;
@@ -135,7 +136,10 @@ __device__ __forceinline__ void visit(const PassArgs &a, PassState<PAIR> &s, uin
         s.sum_b += cb;
         s.zero_b += (cb == 0u);
         if (ca != 0u && cb != 0u) {
-            const double d = delta_m_of(ca, a.nr_a) - delta_m_of(cb, a.nr_b);
+            // the table holds delta_m_of(c, N_rays) itself, so both branches give the same value
+            const double da = ca < (uint32_t)DM_TBL ? tbl[ca] : delta_m_of(ca, a.nr_a);
+            const double db = cb < (uint32_t)DM_TBL ? tbl[DM_TBL + cb] : delta_m_of(cb, a.nr_b);
+            const double d = da - db;
             s.rms += d * d;
             s.n_both += 1;
         }
@@ -145,12 +149,16 @@ __device__ __forceinline__ void visit(const PassArgs &a, PassState<PAIR> &s, uin
 template <bool PAIR>
 __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(const PassArgs a) {
     __shared__ uint32_t lds[PAIR ? 2 * LDS_BINS : LDS_BINS];
+    __shared__ double tbl[PAIR ? 2 * DM_TBL : 1];
     __shared__ double red_d[PASS_THREADS / 64];
     __shared__ unsigned long long red_u[5][PASS_THREADS / 64];
     __shared__ unsigned int red_m[2][PASS_THREADS / 64];
     uint32_t *lds_a = lds;
     uint32_t *lds_b = PAIR ? lds + LDS_BINS : lds;
     for (int k = threadIdx.x; k < (PAIR ? 2 : 1) * LDS_BINS; k += PASS_THREADS) lds[k] = 0u;
+    if (PAIR)
+        for (int k = threadIdx.x; k < 2 * DM_TBL; k += PASS_THREADS)
+            tbl[k] = delta_m_of((uint32_t)(k % DM_TBL), k < DM_TBL ? a.nr_a : a.nr_b);
     __syncthreads();
 
     PassState<PAIR> s;
@@ -164,15 +172,15 @@ __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(const PassArgs a) {
         for (int64_t q = gid; q < n4; q += stride) {
             const uint4 x = va[q];
             const uint4 y = PAIR ? vb[q] : make_uint4(0u, 0u, 0u, 0u);
-            visit<PAIR>(a, s, x.x, y.x, lds_a, lds_b);
-            visit<PAIR>(a, s, x.y, y.y, lds_a, lds_b);
-            visit<PAIR>(a, s, x.z, y.z, lds_a, lds_b);
-            visit<PAIR>(a, s, x.w, y.w, lds_a, lds_b);
+            visit<PAIR>(a, s, x.x, y.x, lds_a, lds_b, tbl);
+            visit<PAIR>(a, s, x.y, y.y, lds_a, lds_b, tbl);
+            visit<PAIR>(a, s, x.z, y.z, lds_a, lds_b, tbl);
+            visit<PAIR>(a, s, x.w, y.w, lds_a, lds_b, tbl);
         }
         tail = n4 * 4;
     }
     for (int64_t p = tail + gid; p < a.npix; p += stride)
-        visit<PAIR>(a, s, a.map_a[p], PAIR ? a.map_b[p] : 0u, lds_a, lds_b);
+        visit<PAIR>(a, s, a.map_a[p], PAIR ? a.map_b[p] : 0u, lds_a, lds_b, tbl);
 
     // Block sums in a fixed order: lanes (butterfly), then waves in index order.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -221,48 +229,97 @@ __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(const PassArgs a) {
     }
 }
 
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;   // histogram bins per block of the tiled scan
+
+int64_t scan_tiles(uint32_t max_count) { return ((int64_t)max_count + 1 + SCAN_TILE - 1) / SCAN_TILE; }
+
+// Inclusive scan of one tile h[i0 .. min(i0 + SCAN_TILE, n)) in place, plus carry;
+// returns the tile's total to every thread.
+__device__ unsigned long long scan_tile(unsigned long long *h, int64_t base, int64_t n, unsigned long long carry,
+                                        unsigned long long *wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+    unsigned long long v[SCAN_ITEMS];
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        run += (i0 + k < n) ? h[i0 + k] : 0ull;
+        v[k] = run;
+    }
+    unsigned long long x = run;   // inclusive scan of the thread totals within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        unsigned long long y = lane < SCAN_THREADS / 64 ? wsum[lane] : 0ull;
+#pragma unroll
+        for (int o = 1; o < SCAN_THREADS / 64; o <<= 1) {
+            const unsigned long long z = __shfl_up(y, o);
+            if (lane >= o) y += z;
+        }
+        if (lane < SCAN_THREADS / 64) wsum[lane] = y;
+    }
+    __syncthreads();
+    const unsigned long long before = carry + (wave ? wsum[wave - 1] : 0ull) + (x - run);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (i0 + k < n) h[i0 + k] = v[k] + before;
+    const unsigned long long total = wsum[SCAN_THREADS / 64 - 1];
+    __syncthreads();
+    return total;
+}
+
+// Tiled scan, phase 1: each block sums one tile of one histogram (blocks [0, ta)
+// are map a's tiles, [ta, ta + tb) map b's) into sums[block].
+__global__ __launch_bounds__(SCAN_THREADS) void tile_sum_kernel(const unsigned long long *ha, int64_t na, int64_t ta,
+                                                                const unsigned long long *hb, int64_t nb,
+                                                                unsigned long long *sums) {
+    __shared__ unsigned long long wsum[SCAN_THREADS / 64];
+    const bool side_a = (int64_t)blockIdx.x < ta;
+    const unsigned long long *h = side_a ? ha : hb;
+    const int64_t n = side_a ? na : nb;
+    const int64_t base = (side_a ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - ta) * SCAN_TILE;
+    unsigned long long t = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * SCAN_THREADS + threadIdx.x;
+        if (i < n) t += h[i];
+    }
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long total = 0;
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) total += wsum[w];
+        sums[blockIdx.x] = total;
+    }
+}
+
+// Tiled scan, phase 3: each tile scanned in place, offset by the inclusive scan of
+// the tile sums before it (phase 2 is scan_kernel over the sums).
+__global__ __launch_bounds__(SCAN_THREADS) void tile_scan_kernel(unsigned long long *ha, int64_t na, int64_t ta,
+                                                                 unsigned long long *hb, int64_t nb,
+                                                                 const unsigned long long *sums) {
+    __shared__ unsigned long long wsum[SCAN_THREADS / 64];
+    const bool side_a = (int64_t)blockIdx.x < ta;
+    unsigned long long *h = side_a ? ha : hb;
+    const int64_t n = side_a ? na : nb;
+    const int64_t tile = side_a ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - ta;
+    const unsigned long long carry = tile ? sums[blockIdx.x - 1] : 0ull;
+    scan_tile(h, tile * SCAN_TILE, n, carry, wsum);
+}
+
 // In-place inclusive prefix sum of h[0..n), one block per array.
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(unsigned long long *ha, int64_t na,
                                                             unsigned long long *hb, int64_t nb) {
     unsigned long long *h = blockIdx.x ? hb : ha;
     const int64_t n = blockIdx.x ? nb : na;
     __shared__ unsigned long long wsum[SCAN_THREADS / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long carry = 0;
-    for (int64_t base = 0; base < n; base += (int64_t)SCAN_THREADS * SCAN_ITEMS) {
-        const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
-        unsigned long long v[SCAN_ITEMS];
-        unsigned long long run = 0;
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            run += (i0 + k < n) ? h[i0 + k] : 0ull;
-            v[k] = run;
-        }
-        unsigned long long x = run;   // inclusive scan of the thread totals within the wave
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wave] = x;
-        __syncthreads();
-        if (wave == 0) {
-            unsigned long long y = lane < SCAN_THREADS / 64 ? wsum[lane] : 0ull;
-#pragma unroll
-            for (int o = 1; o < SCAN_THREADS / 64; o <<= 1) {
-                const unsigned long long z = __shfl_up(y, o);
-                if (lane >= o) y += z;
-            }
-            if (lane < SCAN_THREADS / 64) wsum[lane] = y;
-        }
-        __syncthreads();
-        const unsigned long long before = carry + (wave ? wsum[wave - 1] : 0ull) + (x - run);
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k)
-            if (i0 + k < n) h[i0 + k] = v[k] + before;
-        carry += wsum[SCAN_THREADS / 64 - 1];
-        __syncthreads();
-    }
+    for (int64_t base = 0; base < n; base += SCAN_TILE) carry += scan_tile(h, base, n, carry, wsum);
 }
 
 struct KsArgs {
@@ -395,8 +452,14 @@ __global__ void max_kernel(const uint32_t *map, int64_t npix, int vec4, uint32_t
         tail = n4 * 4;
     }
     for (int64_t p = tail + gid; p < npix; p += stride) m = max(m, map[p]);
+    __shared__ unsigned int wmax[4];
     m = wave_max(m);
-    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int b = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        if (b) atomicMax(out, b);
+    }
 }
 
 __global__ void delta_m_kernel(const uint32_t *map, int64_t npix, double n_rays, double *dm) {
@@ -440,7 +503,8 @@ double rs_rays_per_pixel(const rs_map_params *params) {
 }
 
 size_t rs_compare_workspace_bytes(uint32_t max_a, uint32_t max_b) {
-    return WS_HIST + hist_bytes(max_a) + hist_bytes(max_b);
+    return WS_HIST + hist_bytes(max_a) + hist_bytes(max_b) +
+           align256(sizeof(unsigned long long) * (size_t)(scan_tiles(max_a) + scan_tiles(max_b)));
 }
 
 int rs_map_max(const uint32_t *map, int64_t npix, uint32_t *max_dev, void *stream) {
@@ -451,7 +515,7 @@ int rs_map_max(const uint32_t *map, int64_t npix, uint32_t *max_dev, void *strea
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, max_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "zeroing the maximum");
-    hipLaunchKernelGGL(max_kernel, dim3(stream_blocks(npix, 256 * 16, 2048)), dim3(256), 0, s, map, npix,
+    hipLaunchKernelGGL(max_kernel, dim3(stream_blocks(npix, 256 * 16, 1024)), dim3(256), 0, s, map, npix,
                        aligned(map, 16) ? 1 : 0, max_dev);
     e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "map maximum kernel");
@@ -535,9 +599,18 @@ int rs_compare_maps(const uint32_t *map_a, const uint32_t *map_b, int64_t npix, 
     hipLaunchKernelGGL(pass_kernel<true>, dim3(blocks), dim3(PASS_THREADS), 0, s, pa);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "compare pass kernel");
 
-    hipLaunchKernelGGL(scan_kernel, dim3(2), dim3(SCAN_THREADS), 0, s, hist_a, (int64_t)max_a + 1, hist_b,
-                       (int64_t)max_b + 1);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "histogram scan kernel");
+    // tiled scan of both histograms: tile sums, their scan, the tiles
+    auto *sums = reinterpret_cast<unsigned long long *>(ws + WS_HIST + hist_bytes(max_a) + hist_bytes(max_b));
+    const int64_t ta = scan_tiles(max_a), tb = scan_tiles(max_b);
+    const int64_t na = (int64_t)max_a + 1, nb = (int64_t)max_b + 1;
+    hipLaunchKernelGGL(tile_sum_kernel, dim3((unsigned)(ta + tb)), dim3(SCAN_THREADS), 0, s,
+                       (const unsigned long long *)hist_a, na, ta, (const unsigned long long *)hist_b, nb, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "histogram tile sums");
+    hipLaunchKernelGGL(scan_kernel, dim3(2), dim3(SCAN_THREADS), 0, s, sums, ta, sums + ta, tb);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "scan of tile sums");
+    hipLaunchKernelGGL(tile_scan_kernel, dim3((unsigned)(ta + tb)), dim3(SCAN_THREADS), 0, s, hist_a, na, ta, hist_b,
+                       nb, (const unsigned long long *)sums);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "histogram tile scans");
 
     KsArgs ka{};
     ka.cum_a = hist_a;

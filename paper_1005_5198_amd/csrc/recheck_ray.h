@@ -3,8 +3,8 @@
 // is full.
 //
 // exact_ray_*: the plain definition, operation for operation —
-//   ray position (Section 3.1 regular grid, cell-centred):
-//       x1 = sx0 + ((double)i + 0.5) * (sw / nx)
+//   ray position (Section 3.1 regular grid, cell-centred, or the ray's random point):
+//       x1 = sx0 + ((double)i + 0.5) * (sw / nx)   or   x1 = sx0 + U1 * sw
 //   Section 2, Eq. (sigma): a1 = sum_k (m_k / r2) * d1 in lens order,
 //       d1 = x1 - X_k, r2 = d1*d1 + d2*d2; a ray with r2 == 0 is singular;
 //   y1 = ((1 - gamma) - sigma_c) * x1 - a1, u = (y1 - tx0) / (tw / npx);
@@ -21,6 +21,7 @@
 #pragma once
 
 #include "rs_internal.h"
+#include "philox.h"
 
 namespace rs {
 
@@ -41,10 +42,21 @@ __device__ __forceinline__ T make_uniform(const T &v) {
 constexpr int CODE_OUT = -1;
 constexpr int CODE_SINGULAR = -2;
 
+// Image-plane position of ray (i, j): the regular grid's cell centre, or the
+// ray's Philox-random point of the shooting rectangle.
+__device__ __forceinline__ void ray_xy(const RecheckArgs &a, int64_t i, int64_t j, double &x1, double &x2) {
+    if (a.random) {
+        random_ray_xy(a.sx0, a.sy0, a.sw, a.sh, a.nx, a.seed, i, j, x1, x2);
+    } else {
+        x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
+        x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    }
+}
+
 template <bool UNIT>
 __device__ inline int exact_ray_thread(const RecheckArgs &a, int64_t i, int64_t j) {
-    const double x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
-    const double x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    double x1, x2;
+    ray_xy(a, i, j, x1, x2);
     double a1 = 0.0, a2 = 0.0;
     for (int64_t k = 0; k < a.n_lens; ++k) {
         const double d1 = x1 - a.lens_xy[2 * k];
@@ -78,8 +90,8 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 template <bool UNIT>
 __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j) {
     const int lane = __lane_id();
-    const double x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
-    const double x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    double x1, x2;
+    ray_xy(a, i, j, x1, x2);
     double a1 = 0.0, a2 = 0.0;
     for (int64_t k0 = 0; k0 < a.n_lens; k0 += 64) {
         const int64_t k = k0 + lane;
@@ -115,8 +127,8 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
 template <bool UNIT>
 __device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
     const double U64 = 1.1102230246251565e-16;  // 2^-53
-    const double x1 = a.sx0 + ((double)i + 0.5) * (a.sw / (double)a.nx);
-    const double x2 = a.sy0 + ((double)j + 0.5) * (a.sh / (double)a.ny);
+    double x1, x2;
+    ray_xy(a, i, j, x1, x2);
     const double c1 = (1.0 - a.gamma) - a.sigma_c;
     const double c2 = (1.0 + a.gamma) - a.sigma_c;
     const double inv_pixw = (double)a.npx / a.tw;

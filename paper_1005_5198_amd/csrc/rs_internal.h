@@ -59,7 +59,28 @@ struct ShootArgs {
     unsigned long long *counters;
     uint32_t *queue;       // chunk-relative ray indices to re-check (mixed)
     uint32_t *qcount;
+    // Random rays (RS_RANDOM_RAYS): the launch's rays are counted into square
+    // bins of the shooting rectangle, sorted by bin, and a block deflects the
+    // rays of one bin relative to the bin's centre.
+    int32_t random;
+    uint64_t seed;
+    int64_t nx;            // ray grid width: the generator counter is j * nx + i
+    double sw, sh;
+    int64_t nbx_r, nby_r;  // bins of this launch
+    double bw, bh;         // bin width and height
+    double inv_bw, inv_bh; // nbx_r / sw, nby_r / sh
+    uint32_t *bin_count;   // [n_bins]
+    uint32_t *bin_offset;  // [n_bins + 1] exclusive prefix sums of bin_count
+    uint32_t *bin_cursor;  // [n_bins] scatter cursors
+    uint32_t *ray_rel;     // [rays] chunk-relative index (j - jc0) * (i1 - i0) + (i - i0), by bin
+    double *ray_x, *ray_y; // [rays] FP64 positions, same order
 };
+
+// Random rays: expected rays per bin (a block's capacity is 2048, so a bin
+// overflows it only beyond seven standard deviations, and then takes a second
+// pass), and the largest launch.
+constexpr int64_t RAND_BIN_RAYS = 1740;
+constexpr int64_t RAND_CHUNK_RAYS = int64_t(1) << 26;
 
 struct RecheckArgs {
     double sx0, sy0, sw, sh;
@@ -76,6 +97,8 @@ struct RecheckArgs {
     unsigned long long *counters;
     uint32_t *queue;       // stage A marks unresolved entries in place
     const uint32_t *qcount;
+    int32_t random;        // Philox-random ray positions (RS_RANDOM_RAYS)
+    uint64_t seed;
 };
 
 // Shoot arguments of a whole window (no chunking): the same values the host
@@ -144,6 +167,8 @@ __host__ __device__ inline RecheckArgs recheck_args_of(const rs_map_params &p, c
     r.counters = counters;
     r.queue = nullptr;
     r.qcount = nullptr;
+    r.random = (p.flags & RS_RANDOM_RAYS) ? 1 : 0;
+    r.seed = p.seed;
     return r;
 }
 
@@ -207,6 +232,8 @@ hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_
                        hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream);
+// Random rays: count into bins, scan, scatter, then deflect bin by bin.
+hipError_t launch_shoot_random(const ShootArgs &a, int mode, hipStream_t stream);
 hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);
 
 hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream);

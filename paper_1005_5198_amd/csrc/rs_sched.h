@@ -138,12 +138,14 @@ class Policy {
     }
 
     // Next step, holding about `target_interactions` ray-lens pairs. The budget
-    // goes to open jobs in order of least remaining work, discounted by age:
-    // remaining / (1 + waited / aging_s). A small request finishes in the next
-    // step instead of queueing behind a large one, and a large one that has
-    // waited long gains priority. Every open job gets at least one 32-row band
-    // per step, so none starves.
-    std::vector<Slice> plan(double target_interactions, double now = 0.0, double aging_s = 0.25) {
+    // goes first to jobs that have waited longer than starve_s since submission
+    // (oldest first), then to the others in order of least remaining work,
+    // discounted by age: remaining / (1 + waited / aging_s). A small request
+    // finishes in the next step instead of queueing behind a large one, and a
+    // large one cannot be postponed past starve_s. Every open job gets at least
+    // one 32-row band per step.
+    std::vector<Slice> plan(double target_interactions, double now = 0.0, double aging_s = 0.25,
+                            double starve_s = 0.5) {
         std::vector<Slice> step;
         std::vector<Job *> open;
         for (Job &j : active_)
@@ -154,7 +156,13 @@ class Policy {
             const double waited = now > j->t_submit ? now - j->t_submit : 0.0;
             return per_row(j) * (double)(j->rows - j->next_row) / (1.0 + waited / aging_s);
         };
-        std::stable_sort(open.begin(), open.end(), [&](const Job *a, const Job *b) { return key(a) < key(b); });
+        auto starved = [&](const Job *j) { return now - j->t_submit > starve_s; };
+        std::stable_sort(open.begin(), open.end(), [&](const Job *a, const Job *b) {
+            const bool sa = starved(a), sb = starved(b);
+            if (sa != sb) return sa;
+            if (sa) return a->t_submit < b->t_submit;
+            return key(a) < key(b);
+        });
         double left = target_interactions;
         for (Job *j : open) {
             int64_t rows = left > 0 ? (int64_t)(left / per_row(j)) : 0;

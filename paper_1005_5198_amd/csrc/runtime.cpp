@@ -35,8 +35,29 @@ struct Plan {
     int64_t rows_per_chunk = 0, n_chunks = 0;
     int64_t queue_cap = 0;   // uint32 entries (mixed only)
     size_t qcount_bytes = 0; // WS_QCOUNT + 4 * n_chunks, 256-aligned
+    // Random rays: bin arrays for the largest number of bins of a launch, and
+    // the sorted ray list (index, x, y) of the largest launch.
+    bool random = false;
+    int64_t bins_cap = 0, rays_cap = 0;
+    size_t bin_count_off = 0, bin_offset_off = 0, bin_cursor_off = 0;
+    size_t rel_off = 0, x_off = 0, y_off = 0;
     size_t bytes = 0;
 };
+
+static size_t a256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Square-ish bins of the shooting rectangle holding about RAND_BIN_RAYS of a
+// launch's rays each (never more bins than that target plus one row).
+static void random_bins(int64_t rays, double sw, double sh, int64_t &nbx, int64_t &nby) {
+    int64_t target = (rays + RAND_BIN_RAYS - 1) / RAND_BIN_RAYS;
+    if (target < 1) target = 1;
+    const double side = std::sqrt(sw * sh / (double)target);
+    double fx = std::floor(sw / side + 0.5);
+    if (!(fx >= 1.0)) fx = 1.0;
+    if (fx > (double)target) fx = (double)target;
+    nbx = (int64_t)fx;
+    nby = (target + nbx - 1) / nbx;
+}
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -57,7 +78,8 @@ int validate(const rs_map_params *p, int64_t n_lens) {
     if (p->nx >= (int64_t(1) << 52) || p->ny >= (int64_t(1) << 52)) return fail(RS_EINVAL, "ray grid too large");
     if (p->i1 - p->i0 > (int64_t(1) << 26)) return fail(RS_EINVAL, "window wider than 2^26 rays");
     if (p->mode != RS_FP32 && p->mode != RS_MIXED) return fail(RS_EINVAL, "mode must be RS_FP32 or RS_MIXED");
-    if (p->flags & ~(RS_ACCUMULATE | RS_EXACT_RECHECK)) return fail(RS_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(RS_ACCUMULATE | RS_EXACT_RECHECK | RS_RANDOM_RAYS))
+        return fail(RS_EINVAL, "unknown flags 0x%x", p->flags);
     if (n_lens < 0) return fail(RS_EINVAL, "n_lens < 0");
     return RS_OK;
 }
@@ -66,7 +88,9 @@ Plan make_plan(const rs_map_params *p) {
     Plan pl;
     pl.W = p->i1 - p->i0;
     pl.H = p->j1 - p->j0;
-    int64_t rows = pl.W > 0 ? CHUNK_RAYS / pl.W : PATCH_Y;
+    pl.random = (p->flags & RS_RANDOM_RAYS) != 0;
+    const int64_t chunk_rays = pl.random ? RAND_CHUNK_RAYS : CHUNK_RAYS;
+    int64_t rows = pl.W > 0 ? chunk_rays / pl.W : PATCH_Y;
     rows = rows / PATCH_Y * PATCH_Y;
     if (rows < PATCH_Y) rows = PATCH_Y;
     pl.rows_per_chunk = rows;
@@ -75,6 +99,29 @@ Plan make_plan(const rs_map_params *p) {
     pl.queue_cap = (p->mode == RS_MIXED) ? rows_cap * pl.W : 0;
     pl.qcount_bytes = (WS_QCOUNT + 4 * (size_t)pl.n_chunks + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
+    if (pl.random && pl.n_chunks > 0) {
+        pl.rays_cap = rows_cap * pl.W;
+        const int64_t last_rows = pl.H - (pl.n_chunks - 1) * rows;
+        int64_t bx, by;
+        random_bins(pl.rays_cap, p->sw, p->sh, bx, by);
+        pl.bins_cap = bx * by;
+        random_bins(last_rows * pl.W, p->sw, p->sh, bx, by);
+        if (bx * by > pl.bins_cap) pl.bins_cap = bx * by;
+        size_t off = a256(pl.bytes);
+        pl.bin_count_off = off;
+        off += a256(4 * (size_t)pl.bins_cap);
+        pl.bin_offset_off = off;
+        off += a256(4 * ((size_t)pl.bins_cap + 1));
+        pl.bin_cursor_off = off;
+        off += a256(4 * (size_t)pl.bins_cap);
+        pl.rel_off = off;
+        off += a256(4 * (size_t)pl.rays_cap);
+        pl.x_off = off;
+        off += a256(8 * (size_t)pl.rays_cap);
+        pl.y_off = off;
+        off += a256(8 * (size_t)pl.rays_cap);
+        pl.bytes = off;
+    }
     return pl;
 }
 
@@ -189,8 +236,23 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
     r.pix_out = pix;
     r.counters = a.counters;
     r.queue = a.queue;
+    r.random = pl.random ? 1 : 0;
+    r.seed = p->seed;
+    if (pl.random) {
+        a.random = 1;
+        a.seed = p->seed;
+        a.nx = p->nx;
+        a.sw = p->sw;
+        a.sh = p->sh;
+        a.bin_count = reinterpret_cast<uint32_t *>(ws + pl.bin_count_off);
+        a.bin_offset = reinterpret_cast<uint32_t *>(ws + pl.bin_offset_off);
+        a.bin_cursor = reinterpret_cast<uint32_t *>(ws + pl.bin_cursor_off);
+        a.ray_rel = reinterpret_cast<uint32_t *>(ws + pl.rel_off);
+        a.ray_x = reinterpret_cast<double *>(ws + pl.x_off);
+        a.ray_y = reinterpret_cast<double *>(ws + pl.y_off);
+    }
 
-    if (shape < 0) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
+    if (shape < 0 && !pl.random) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
     hipEvent_t t_first = nullptr, t_last = nullptr;
     if (kernel_ms) {
         *kernel_ms = 0.0f;
@@ -205,7 +267,16 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         void *tok = nullptr;
         profile_begin(stream, &tok);
         if (kernel_ms && hipEventRecord(t_first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
-        e = launch_shoot(a, p->mode, shape, stream);
+        if (pl.random) {
+            random_bins((a.jc1 - a.jc0) * pl.W, p->sw, p->sh, a.nbx_r, a.nby_r);
+            a.bw = p->sw / (double)a.nbx_r;
+            a.bh = p->sh / (double)a.nby_r;
+            a.inv_bw = (double)a.nbx_r / p->sw;
+            a.inv_bh = (double)a.nby_r / p->sh;
+            e = launch_shoot_random(a, p->mode, stream);
+        } else {
+            e = launch_shoot(a, p->mode, shape, stream);
+        }
         if (e != hipSuccess) return hip_fail(e, "deflection kernel");
         if (kernel_ms) {
             float ms = 0.0f;

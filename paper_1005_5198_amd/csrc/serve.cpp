@@ -142,7 +142,7 @@ void rs_server::finish(Request &r, int state, int error) {
 // Plan and enqueue one step (called with the lock held). Returns false if there was nothing to run.
 bool rs_server::launch_step() {
     const double target = rate * (cfg.slice_ms > 0 ? cfg.slice_ms : 10.0) * 1e-3;
-    std::vector<Slice> slices = policy.plan(target, now_s());
+    std::vector<Slice> slices = policy.plan(target, now_s(), 0.25, cfg.starve_s > 0 ? cfg.starve_s : 0.5);
     if (slices.empty()) return false;
     std::vector<rs_map_request> batch;
     batch.reserve(slices.size());
@@ -394,6 +394,7 @@ int rs_server_submit(rs_server *s, const rs_map_params *params, const double *le
     if (!s || !params || !ticket) return fail(RS_EINVAL, "NULL argument");
     int rc = validate(params, n_lens);
     if (rc) return rc;
+    if (params->flags & RS_RANDOM_RAYS) return fail(RS_EINVAL, "the server makes regular-grid maps only");
     if (n_lens > 0 && !lens_xy_host) return fail(RS_EINVAL, "lens_xy is NULL");
     const double rays = (double)(params->i1 - params->i0) * (double)(params->j1 - params->j0);
     if (rays >= 4294967296.0) return fail(RS_EINVAL, "window holds 2^32 rays or more");

@@ -58,6 +58,7 @@ int rs_tune(const rs_map_params *params, const double *lens_xy, const double *le
             uint32_t *scratch_map, void *workspace, size_t workspace_bytes, int64_t sample_rays, void *stream,
             rs_tune_result *result_host) {
     if (!params || !result_host || !scratch_map) return fail(RS_EINVAL, "NULL argument");
+    if (params->flags & RS_RANDOM_RAYS) return fail(RS_EINVAL, "the tuner times regular-grid maps only");
     rs_map_params p = *params;
     p.flags &= ~RS_ACCUMULATE;
     const int64_t W = p.i1 - p.i0, H = p.j1 - p.j0;

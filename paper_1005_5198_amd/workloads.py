@@ -215,6 +215,30 @@ def paper_point(sigma: float, gamma: float, sigma_c: float = 0.0, n_pix_side: in
     return MapSpec(f"paper_sigma{sigma}_gamma{gamma}", p, lens, None)
 
 
+def phi_fiducial(seed: int = 6, sigma_star: float = 0.45, n_star: int = 1_000_000, n_pix_side: int = 2500,
+                 rays_per_px: float = 500.0) -> MapSpec:
+    """The Phi_fiducial scale of Section 3.1: 2500^2 pixels, N* = 1e6 lenses, 500 rays per pixel.
+
+    sigma* = 0.45 in unit-mass lenses, no smooth matter, no shear. The disc holds
+    N* = sigma* R^2 lenses; the map side L follows from the paper-rule radius
+    R = 1.5 x half-diagonal(L/|1-sigma|, L/|1-sigma|) + 2, and the shooting square is
+    the macro model's preimage of the map, side L/|1-sigma|. A pixel receives
+    rays_per_px rays on average (mean over the map), so the ray grid holds
+    N_pix * rays_per_px rays (the count in the paper's Phi = N_FLOP N_pix N* N_rays):
+    55902^2 = 3.125e9 rays and 3.1e15 interactions.
+    """
+    rng = np.random.default_rng(seed)
+    lam = abs(1.0 - sigma_star)
+    radius = math.sqrt(n_star / sigma_star)
+    l_map = (radius - 2.0) * lam / (1.5 * 0.5 * math.sqrt(2.0))
+    side = l_map / lam
+    n = int(round(math.sqrt(n_pix_side * n_pix_side * rays_per_px)))
+    lens = lenses_in_disc(n_star_for_disc(sigma_star, radius), radius, rng)
+    p = make_params(sigma_star, 0.0, 0.0, (-side / 2, -side / 2, side, side, n, n),
+                    (-l_map / 2, -l_map / 2, l_map, l_map, n_pix_side, n_pix_side))
+    return MapSpec("phi_fiducial_1e6_lenses_2500px", p, lens, None)
+
+
 CONFIGS = {"c0": config0, "c1": config1, "c2": config2}
 
 

@@ -86,6 +86,34 @@ int main() {
         while (p.active()) { p.step_done(p.plan(128 * 1e5), 1.0 + steps); ++steps; if (steps > 100) break; }
         put("srpt_total_steps", std::to_string(steps));
     }
+    // 3b. starvation guard: a large job older than starve_s goes before a small new one
+    {
+        Policy p(1 << 30, 8);
+        Job big = job(1, 1, 1000, 1000, 100);
+        big.t_submit = 0.0;
+        Job small = job(2, 1, 1000, 70, 100);
+        small.t_submit = 0.9;
+        p.submit(big);
+        p.submit(small);
+        auto fits = [](Job &) { return true; };
+        p.admit(0.0, fits, nullptr);
+        auto show = [](const std::vector<Slice> &s) {
+            std::string sl = "[";
+            for (size_t i = 0; i < s.size(); ++i)
+                sl += (i ? "," : "") + std::string("[") + std::to_string(s[i].ticket) + "," +
+                      std::to_string(s[i].row0) + "," + std::to_string(s[i].row1) + "]";
+            return sl + "]";
+        };
+        std::vector<Slice> a = p.plan(128 * 1e5, 1.0, 0.25, 0.5);   // big has waited 1.0 s > 0.5 s
+        put("starve_step1", show(a));
+        p.step_done(a, 1.0);
+        Policy q(1 << 30, 8);
+        big.t_submit = 0.8;
+        q.submit(big);
+        q.submit(small);
+        q.admit(0.0, fits, nullptr);
+        put("starve_none", show(q.plan(128 * 1e5, 1.0, 0.25, 0.5)));  // neither has waited 0.5 s
+    }
     // 4. cancellation of a waiting and of a running job
     {
         Policy p(1 << 30, 1);

@@ -128,3 +128,22 @@ def test_map_statistics_validation(lib):
     assert lib.rs_map_histogram(fake, 16, 0xFFFFFFFF, fake, None) == L.RS_EINVAL
     assert lib.rs_delta_m(fake, 16, float("nan"), fake, None) == L.RS_EINVAL
     assert lib.rs_map_max(fake + 2, 16, fake, None) == L.RS_EINVAL
+
+
+def test_random_rays_flag_validation(lib):
+    """Random rays are accepted by the single-map entry points and refused by batches,
+    the server and the tuner before anything reaches a device."""
+    from paper_1005_5198_amd import _lib as L, api, workloads as w
+    s = w.config2()
+    p = dict(s.params)
+    p.update(random_rays=1, seed=123)
+    c = api.to_params(p)
+    assert c.flags & L.RS_RANDOM_RAYS and c.seed == 123
+    grid_bytes = api.workspace_bytes(s.params, s.n_lens)
+    rand_bytes = lib.rs_workspace_bytes(ctypes.byref(c), s.n_lens)
+    # the sorted ray list (index + two FP64 coordinates) of one launch is in the workspace
+    assert rand_bytes >= 20 * 19200 * 3840 and rand_bytes > grid_bytes
+    req = L.MapRequest(c, 1 << 20, None, s.n_lens, 1 << 21)
+    ws = 1 << 22
+    assert lib.rs_make_maps(ctypes.byref(req), 1, ws, 1 << 40, None) == L.RS_EINVAL
+    assert b"random rays" in lib.rs_last_error()

@@ -1,0 +1,140 @@
+"""Random ray positions (RS_RANDOM_RAYS) on the HIP path vs the FP64 oracle (needs an MI355X).
+
+The oracle and the kernels each implement Philox4x64-10 and the position
+formula on their own; the oracle's generator is pinned to numpy's. The bar is
+the regular grid's: in mixed mode every ray's pixel and the whole map equal
+the oracle's, bit for bit; in FP32 mode at most 1e-4 of the rays change pixel.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stats as S
+from paper_1005_5198_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1005_5198_amd as rs_mod
+    oracle.build(force=False)
+    return rs_mod
+
+
+def randomized(spec, seed):
+    p = dict(spec.params)
+    p.update(random_rays=1, seed=seed)
+    return w.MapSpec(spec.name + f"_random{seed}", p, spec.lens_xy, spec.lens_m)
+
+
+def check_exact(rs, spec):
+    say("random mixed-exact", spec.name, spec.n_rays, "rays", spec.n_lens, "lenses")
+    m_o, st_o = oracle.make_map(spec.params, spec.lens_xy, spec.lens_m)
+    m_g, st_g = rs.make_map(spec.params, spec.lens_xy, spec.lens_m, mode="mixed", return_stats=True)
+    m_g = m_g.cpu().numpy()
+    say("  re-checked", st_g["rays_rechecked"], "oracle near-edge", st_o["near_edge"])
+    assert np.array_equal(m_g, m_o), f"map differs in {int(np.count_nonzero(m_g != m_o))} pixels"
+    assert st_g["rays_in_map"] == st_o["rays_in_map"] and st_g["rays_out"] == st_o["rays_out"]
+    assert st_g["rays_singular"] == st_o["rays_singular"] and st_g["rays_shot"] == spec.n_rays
+    return st_g
+
+
+def check_pixels(rs, spec, fp32_budget=1e-4):
+    say("random pixels", spec.name)
+    pix_o, _, _ = oracle.ray_pixels(spec.params, spec.lens_xy, spec.lens_m)
+    pix_m = rs.ray_pixels(spec.params, spec.lens_xy, spec.lens_m, mode="mixed").cpu().numpy().astype(np.int64)
+    assert np.array_equal(pix_m, pix_o), f"mixed: {int(np.count_nonzero(pix_m != pix_o))} rays differ"
+    pix_f = rs.ray_pixels(spec.params, spec.lens_xy, spec.lens_m, mode="fp32").cpu().numpy().astype(np.int64)
+    changed = np.count_nonzero(pix_f != pix_o) / max(len(pix_o), 1)
+    say(f"  fp32 changed-ray fraction {changed:.3e}")
+    assert changed <= fp32_budget
+
+
+def test_random_config0_map_and_pixels(rs):
+    s = randomized(w.config0(), 5)
+    check_exact(rs, s)
+    check_pixels(rs, s)
+
+
+def test_random_identity_matches_oracle_and_scatters(rs):
+    """No lenses: the random map equals the oracle's, and its counts scatter around N_rays
+    (the regular grid's map is flat)."""
+    p = w.make_params(0.0, 0.0, 0.0, (-6.0, -3.0, 12.0, 6.0, 480, 240), (-6.0, -3.0, 12.0, 6.0, 48, 24))
+    grid = rs.make_map(p, np.zeros((0, 2))).cpu().numpy()
+    assert np.all(grid == 100)
+    s = randomized(w.MapSpec("identity", p, np.zeros((0, 2)), None), 3)
+    st = check_exact(rs, s)
+    m = rs.make_map(s.params, s.lens_xy, mode="mixed").cpu().numpy()
+    assert int(m.sum()) == 480 * 240 and st["rays_out"] == 0
+    var = float(m.astype(np.float64).var())
+    say("  identity random-ray count variance", var, "(multinomial: about 100)")
+    assert 70.0 < var < 130.0
+
+
+def test_random_config2_windows(rs):
+    s = randomized(w.config2(), 11)
+    for (i0, i1, j0, j1) in ((9000, 10000, 1800, 1864), (0, 64, 0, 3840), (19199, 19200, 3839, 3840)):
+        sub = s.window(i0, i1, j0, j1)
+        check_exact(rs, sub)
+        check_pixels(rs, sub)
+
+
+def test_random_with_masses(rs):
+    s = w.config0()
+    rng = np.random.default_rng(17)
+    masses = rng.uniform(0.1, 2.0, size=s.n_lens)
+    sub = randomized(w.MapSpec("c0_masses", s.params, s.lens_xy, masses), 9).window(0, 1024, 200, 456)
+    check_exact(rs, sub)
+
+
+def test_random_windows_sum_to_full_map(rs):
+    s = randomized(w.config0(), 21)
+    full = rs.make_map(s.params, s.lens_xy, mode="mixed").cpu().numpy()
+    xy, _ = rs.lens_tensors(s.lens_xy)
+    acc = None
+    for (j0, j1) in ((0, 301), (301, 777), (777, 1024)):
+        q = dict(s.params)
+        q.update(j0=j0, j1=j1)
+        acc = rs.make_map(q, xy, None, mode="mixed", out=acc, accumulate=acc is not None)
+    assert np.array_equal(acc.cpu().numpy(), full)
+
+
+def test_random_config2_full_map(rs):
+    """The full 19200 x 3840 random-ray map: determinism, conservation, sampled rays vs the oracle,
+    and the statistics against the regular-grid map of the same lenses (N_rays = 2.44)."""
+    s = randomized(w.config2(), 2)
+    say("config2 random full map")
+    xy, _ = rs.lens_tensors(s.lens_xy)
+    ws = rs.new_workspace(s.params, s.n_lens, "mixed")
+    a = rs.make_map(s.params, xy, None, mode="mixed", workspace=ws)
+    st = rs.read_stats(ws)
+    b = rs.make_map(s.params, xy, None, mode="mixed", workspace=ws)
+    assert torch.equal(a, b) and rs.read_stats(ws) == st
+    assert st["rays_in_map"] + st["rays_out"] + st["rays_singular"] == s.n_rays
+    say(f"  re-checked {st['rays_rechecked'] / s.n_rays:.3%}")
+    rng = np.random.default_rng(8)
+    for _ in range(4):
+        i0 = int(rng.integers(0, 19200 - 64))
+        j0 = int(rng.integers(0, 3840 - 16))
+        sub = s.window(i0, i0 + 64, j0, j0 + 16)
+        pix_o, _, _ = oracle.ray_pixels(sub.params, sub.lens_xy)
+        pix_m = rs.ray_pixels(sub.params, xy, None, mode="mixed").cpu().numpy().astype(np.int64)
+        assert np.array_equal(pix_m, pix_o)
+    grid = rs.make_map(w.config2().params, xy, None, mode="mixed")
+    nr = rs.rays_per_pixel(s.params)
+    cmp = rs.compare_maps(a.view(-1), grid.view(-1), nr, nr)
+    say("  random vs grid: rms dm", cmp["rms_dm"], "D", cmp["ks_d"], "P(KS)", cmp["ks_p"],
+        "mean mu", cmp["mean_mu_a"], cmp["mean_mu_b"])
+    assert abs(cmp["mean_mu_a"] / cmp["mean_mu_b"] - 1.0) < 5e-3

@@ -44,6 +44,13 @@ def test_shortest_remaining_first(res):
     assert res["srpt_total_steps"] == 1 + -(-(1000 - 32) // 128)
 
 
+def test_starvation_guard(res):
+    # the big job has waited past starve_s: it takes the budget (128 rows), the small one a band
+    assert res["starve_step1"] == [[1, 0, 128], [2, 0, 32]]
+    # neither has waited that long: least remaining work first, as before
+    assert res["starve_none"] == [[2, 0, 70], [1, 0, 32]]
+
+
 def test_cancellation(res):
     assert res["cancel_dropped"] == [2]
     assert res["cancel_plan_after"] == 0    # a cancelled job gets no more slices

@@ -92,3 +92,15 @@ def test_config4_arrivals_are_poisson():
     gaps = np.diff(times)
     assert np.all(gaps >= 0) and abs(gaps.mean() - 0.1) < 0.02
     assert len(maps) == 400
+
+
+def test_phi_fiducial_scale():
+    """Section 3.1's Phi_fiducial: N_FLOP N_pix N* N_rays = 10 x 2500^2 x 1e6 x 500 = 3.1e16."""
+    s = w.phi_fiducial()
+    assert s.n_lens == 1_000_000
+    assert s.params["npx"] == s.params["npy"] == 2500
+    assert abs(10 * s.interactions - 10 * 2500 ** 2 * 1e6 * 500) / 3.125e16 < 1e-4
+    # the disc radius is the paper rule's for this map side
+    assert abs(w.paper_rule_radius(0.45, 0.0, s.params["tw"]) - math.sqrt(1e6 / 0.45)) < 1e-9
+    r = np.hypot(s.lens_xy[:, 0], s.lens_xy[:, 1])
+    assert r.max() <= math.sqrt(1e6 / 0.45)
