@@ -17,8 +17,9 @@ Prints ONE JSON line:
 Also reported: the plain-FP32 mode rate, the re-check fraction, the 64-map
 batch (one persistent launch) against the same maps one at a time, and the
 request loop (continuous batching, Poisson arrivals) against the same arrivals
-served one at a time, with maps/s and p50/p99 latency, and the map comparison
-(RMS of dm, K-S test) of two 4096^2 maps.
+served one at a time, with maps/s and p50/p99 latency, the map comparison
+(RMS of dm, K-S test) of two 4096^2 maps, and the same map in the far-field
+expansion mode (same count map, far fewer operations).
 """
 from __future__ import annotations
 
@@ -52,6 +53,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-map batch vs one-at-a-time")
     ap.add_argument("--no-serve", action="store_true", help="skip the request loop vs one-at-a-time")
     ap.add_argument("--no-stats", action="store_true", help="skip the map-comparison statistics timing")
+    ap.add_argument("--no-farfield", action="store_true", help="skip the far-field expansion mode timing")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-rho", type=float, default=0.8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -173,7 +175,7 @@ def main():
             rs.make_map(spec.params, xy, m, mode="fp32", out=out, workspace=ws32)
         torch.cuda.synchronize()
         result["fp32_mode_value"] = inter * n32 / (time.perf_counter() - t)
-    if not (args.no_batched and args.no_serve and args.no_stats):
+    if not (args.no_batched and args.no_serve and args.no_stats and args.no_farfield):
         from paper_1005_5198_amd import bench_extra
         if not args.no_batched:
             result["batched"] = bench_extra.batched(rs, mode=args.mode)
@@ -182,6 +184,8 @@ def main():
                                                   mode=args.mode)
         if not args.no_stats:
             result["map_stats"] = bench_extra.map_stats(rs)
+        if not args.no_farfield:
+            result["far_field"] = bench_extra.far_field(rs)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(result), flush=True)

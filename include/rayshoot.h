@@ -36,6 +36,17 @@
  *             cannot place run the exact sequence. The count map equals the
  *             FP64 definition's map.
  *   RS_FP32   the same FP32 sum, binned directly (no bound, no re-check).
+ *   RS_FARFIELD  the tree codes' idea (Section 2, Eq. (hierarchical): distant
+ *             lenses grouped, with higher multipoles) taken to all orders: per
+ *             64 x 32-ray patch, lenses farther than 4 half-diagonals enter an
+ *             order-16 FP64 local expansion of the deflection about the patch
+ *             centre, nearer ones are summed directly, and each ray carries a
+ *             rigorous bound (truncation + rounding + the definition's own
+ *             rounding); rays within it of a pixel edge get the same FP64
+ *             re-check. The count map equals the FP64 definition's map, at
+ *             about 100 FP64 operations per lens and patch instead of 2048
+ *             interactions. Single maps only (not random rays, batches, the
+ *             server or the tuner).
  *
  * Conventions for every call:
  *   - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
@@ -68,6 +79,7 @@ extern "C" {
 
 #define RS_FP32 0
 #define RS_MIXED 1
+#define RS_FARFIELD 2
 
 #define RS_ACCUMULATE 1      /* flag: add to the map instead of zeroing it first */
 #define RS_EXACT_RECHECK 2   /* flag (RS_MIXED): re-check every queued ray with the definition's exact
@@ -87,7 +99,7 @@ typedef struct {
     double tx0, ty0;        /* lower-left corner of the source map */
     double tw, th;          /* source map width and height, > 0 */
     int64_t npx, npy;       /* source pixels, > 0; the map is uint32 [npy][npx] row-major */
-    int32_t mode;           /* RS_FP32 or RS_MIXED */
+    int32_t mode;           /* RS_FP32, RS_MIXED or RS_FARFIELD */
     int32_t flags;          /* 0 or an OR of RS_ACCUMULATE, RS_EXACT_RECHECK, RS_RANDOM_RAYS */
     uint64_t seed;          /* RS_RANDOM_RAYS: the generator key's first word */
 } rs_map_params;

@@ -19,6 +19,7 @@ RS_EBUSY = -4
 RS_ECANCELED = -5
 RS_FP32 = 0
 RS_MIXED = 1
+RS_FARFIELD = 2
 RS_ACCUMULATE = 1
 RS_EXACT_RECHECK = 2
 RS_RANDOM_RAYS = 4

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib as L
 
-MODES = {"fp32": L.RS_FP32, "mixed": L.RS_MIXED}
+MODES = {"fp32": L.RS_FP32, "mixed": L.RS_MIXED, "farfield": L.RS_FARFIELD}
 
 
 def to_params(p: dict, mode: str = "mixed", accumulate: bool = False, exact_recheck: bool = False) -> L.MapParams:

@@ -217,3 +217,26 @@ def phi_fiducial(rs, rows: int = 64, full: bool = False, band_rows: int = 2400, 
             "pct_fp32_peak": 10.0 * rate / 157.3e12, "recheck_fraction": total["rays_rechecked"] / spec.n_rays,
             "rays_in_map": total["rays_in_map"], "rays_out": total["rays_out"],
             "map_sum": int(out.to(torch.int64).sum().item())}
+
+
+def far_field(rs, reps: int = 5) -> dict:
+    """The config-2 map in RS_FARFIELD mode (per-patch FP64 local expansion of the distant
+    lenses, bound, FP64 re-check): time per map, the direct-sum interactions it stands for per
+    second, and whether the map equals the mixed (direct) mode's, bit for bit."""
+    spec = w.config2()
+    xy, _ = rs.lens_tensors(spec.lens_xy)
+    ws = rs.new_workspace(spec.params, spec.n_lens, "mixed")
+    out = torch.empty((spec.params["npy"], spec.params["npx"]), dtype=torch.uint32, device="cuda")
+    ref = rs.make_map(spec.params, xy, None, mode="mixed", workspace=ws).clone()
+    rs.make_map(spec.params, xy, None, mode="farfield", out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        rs.make_map(spec.params, xy, None, mode="farfield", out=out, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    st = rs.read_stats(ws)
+    return {"workload": "config2", "ms_per_map": dt * 1e3, "maps_per_s": 1.0 / dt,
+            "direct_equivalent_interactions_per_s": spec.interactions / dt,
+            "recheck_fraction": st["rays_rechecked"] / spec.n_rays,
+            "equals_mixed_map": bool(torch.equal(out, ref))}

@@ -47,6 +47,8 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
         int rc = validate(&r.params, r.n_lens);
         if (rc) return fail(rc, "request %d: %s", k, rs_last_error());
         if (r.params.mode != mode) return fail(RS_EINVAL, "request %d: every request of a batch needs the same mode", k);
+        if (r.params.mode == RS_FARFIELD)
+            return fail(RS_EINVAL, "request %d: RS_FARFIELD maps are made by rs_make_map only, not in batches", k);
         if (r.params.flags & RS_RANDOM_RAYS)
             return fail(RS_EINVAL, "request %d: random rays are made by rs_make_map only, not in batches", k);
         if (!r.map) return fail(RS_EINVAL, "request %d: map is NULL", k);

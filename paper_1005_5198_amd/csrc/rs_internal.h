@@ -232,6 +232,8 @@ hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_
                        hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t stream);
+// Far-field expansion (RS_FARFIELD): one block per patch, FP64 local expansion plus near lenses.
+hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream);
 // Random rays: count into bins, scan, scatter, then deflect bin by bin.
 hipError_t launch_shoot_random(const ShootArgs &a, int mode, hipStream_t stream);
 hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);

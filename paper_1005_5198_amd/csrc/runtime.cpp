@@ -77,7 +77,10 @@ int validate(const rs_map_params *p, int64_t n_lens) {
                     (long long)p->i1, (long long)p->j0, (long long)p->j1, (long long)p->nx, (long long)p->ny);
     if (p->nx >= (int64_t(1) << 52) || p->ny >= (int64_t(1) << 52)) return fail(RS_EINVAL, "ray grid too large");
     if (p->i1 - p->i0 > (int64_t(1) << 26)) return fail(RS_EINVAL, "window wider than 2^26 rays");
-    if (p->mode != RS_FP32 && p->mode != RS_MIXED) return fail(RS_EINVAL, "mode must be RS_FP32 or RS_MIXED");
+    if (p->mode != RS_FP32 && p->mode != RS_MIXED && p->mode != RS_FARFIELD)
+        return fail(RS_EINVAL, "mode must be RS_FP32, RS_MIXED or RS_FARFIELD");
+    if (p->mode == RS_FARFIELD && (p->flags & RS_RANDOM_RAYS))
+        return fail(RS_EINVAL, "RS_FARFIELD works on the regular grid only");
     if (p->flags & ~(RS_ACCUMULATE | RS_EXACT_RECHECK | RS_RANDOM_RAYS))
         return fail(RS_EINVAL, "unknown flags 0x%x", p->flags);
     if (n_lens < 0) return fail(RS_EINVAL, "n_lens < 0");
@@ -96,7 +99,7 @@ Plan make_plan(const rs_map_params *p) {
     pl.rows_per_chunk = rows;
     pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
     const int64_t rows_cap = pl.H < rows ? pl.H : rows;
-    pl.queue_cap = (p->mode == RS_MIXED) ? rows_cap * pl.W : 0;
+    pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
     pl.qcount_bytes = (WS_QCOUNT + 4 * (size_t)pl.n_chunks + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
     if (pl.random && pl.n_chunks > 0) {
@@ -252,7 +255,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         a.ray_y = reinterpret_cast<double *>(ws + pl.y_off);
     }
 
-    if (shape < 0 && !pl.random) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
+    if (shape < 0 && !pl.random && p->mode != RS_FARFIELD) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
     hipEvent_t t_first = nullptr, t_last = nullptr;
     if (kernel_ms) {
         *kernel_ms = 0.0f;
@@ -274,6 +277,8 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
             a.inv_bw = (double)a.nbx_r / p->sw;
             a.inv_bh = (double)a.nby_r / p->sh;
             e = launch_shoot_random(a, p->mode, stream);
+        } else if (p->mode == RS_FARFIELD) {
+            e = launch_farfield(a, stream);
         } else {
             e = launch_shoot(a, p->mode, shape, stream);
         }
@@ -287,7 +292,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         }
         rc = profile_end(stream, tok, (double)(a.jc1 - a.jc0) * (double)pl.W * (double)n_lens);
         if (rc) return rc;
-        if (p->mode == RS_MIXED) {
+        if (p->mode != RS_FP32) {
             r.jc0 = a.jc0;
             r.qcount = a.qcount;
             e = launch_recheck(r, (a.jc1 - a.jc0) * pl.W, (p->flags & RS_EXACT_RECHECK) != 0, stream);

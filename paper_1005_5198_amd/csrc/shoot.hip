@@ -657,6 +657,219 @@ __global__ __launch_bounds__(64 * FREE_WAVES) void shoot_free_kernel(const Shoot
         shoot_free_chunk<FREE_RR, FREE_WAVES, UNIT, MODE, PIX>(a, base, end, ox, oy, hx, hy, sm);
 }
 
+// ---------------------------------------------------------------------------
+// Far-field expansion (RS_FARFIELD): the paper's tree codes group distant
+// lenses into pseudo-lenses with higher multipoles (Section 2, Eq.
+// (hierarchical)); here every lens farther than FAR_RATIO h from a 64 x 32-ray
+// patch (h = the patch's half-diagonal) enters a local expansion of the
+// deflection about the patch centre z0, to order FAR_P:
+//     sum_k m_k / (z - z_k) = sum_n (-w)^n c_n,  c_n = sum_k m_k t_k^(n+1),
+//     t_k = 1 / (z0 - z_k),  w = z - z0,  |w| <= h,  |t_k| h <= 1 / FAR_RATIO,
+// with z = x1 + i x2 and the deflection (a1, a2) = (Re, -Im) of the sum. Nearer
+// lenses are summed directly. All of it is FP64, and every ray carries a
+// rigorous bound on its error (series truncation, the coefficients' and the
+// evaluation's rounding) plus the definition's own rounding; rays within it of
+// a pixel edge go to the FP64 re-check, so the map equals the definition's.
+// Per patch the expansion costs about 100 FP64 operations per lens instead of
+// 2048 rays x 10 per lens.
+// ---------------------------------------------------------------------------
+constexpr int FAR_P = 16;
+constexpr double FAR_RATIO = 4.0;
+constexpr int FAR_THREADS = 256;
+constexpr int FAR_ROWS = PATCH_Y / (FAR_THREADS / PATCH_X);   // rays per thread (8)
+constexpr int NEAR_EXP = 512;
+
+struct FarSmem {
+    double near_x[NEAR_EXP], near_y[NEAR_EXP], near_m[NEAR_EXP];
+    int near_count;
+    double part[FAR_THREADS / 64][2 * FAR_P + 4];
+    double coef[2 * FAR_P + 4];
+};
+
+__device__ __forceinline__ double rcp64(double r2) {
+    double rc = __builtin_amdgcn_rcp(r2);
+    double e = __builtin_fma(-r2, rc, 1.0);
+    rc = __builtin_fma(rc, e, rc);
+    e = __builtin_fma(-r2, rc, 1.0);
+    return __builtin_fma(rc, e, rc);
+}
+
+template <bool UNIT, bool PIX>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a) {
+    __shared__ FarSmem sm;
+    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t patch = blockIdx.x;
+    const int64_t pbx = patch % a.nbx, pby = patch / a.nbx;
+    const int64_t ib = a.i0 + pbx * PATCH_X;
+    const int64_t jb = a.jc0 + pby * PATCH_Y;
+    const double ox = a.sx0 + ((double)ib + 0.5 * PATCH_X) * a.spx;
+    const double oy = a.sy0 + ((double)jb + 0.5 * PATCH_Y) * a.spy;
+    const double hx = (0.5 * PATCH_X + 1.0) * a.spx;
+    const double hy = (0.5 * PATCH_Y + 1.0) * a.spy;
+    const double h = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
+    const double near_r2 = (FAR_RATIO * h) * (FAR_RATIO * h);
+    if (tid == 0) sm.near_count = 0;
+    __syncthreads();
+
+    // Phase 1: coefficients and the far lenses' bound terms, lenses split over the threads.
+    double c1[FAR_P], c2[FAR_P];
+#pragma unroll
+    for (int n = 0; n < FAR_P; ++n) {
+        c1[n] = 0.0;
+        c2[n] = 0.0;
+    }
+    double sfar = 0.0, trunc = 0.0, sdef = 0.0, nfar = 0.0;
+    for (int64_t k = tid; k < a.n_lens; k += FAR_THREADS) {
+        const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
+        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
+        const double d1 = ox - X, d2 = oy - Y;
+        const double r2 = d1 * d1 + d2 * d2;
+        if (!(r2 >= near_r2)) {
+            const int q = atomicAdd(&sm.near_count, 1);
+            if (q < NEAR_EXP) {
+                sm.near_x[q] = X;
+                sm.near_y[q] = Y;
+                sm.near_m[q] = m;
+            }
+            continue;
+        }
+        const double inv = rcp64(r2);
+        const double t1 = d1 * inv, t2 = -d2 * inv;   // t = 1 / (z0 - z_k)
+        double p1 = m * t1, p2 = m * t2;
+        c1[0] += p1;
+        c2[0] += p2;
+#pragma unroll
+        for (int n = 1; n < FAR_P; ++n) {
+            const double q1 = __builtin_fma(p1, t1, -p2 * t2);
+            const double q2 = __builtin_fma(p1, t2, p2 * t1);
+            p1 = q1;
+            p2 = q2;
+            c1[n] += p1;
+            c2[n] += p2;
+        }
+        const double ad = sqrt(r2);
+        const double am = fabs(m);
+        const double rho = h / ad;
+        const double rho2 = rho * rho, rho4 = rho2 * rho2, rho8 = rho4 * rho4, rho16 = rho8 * rho8;
+        sfar += am / ad;
+        trunc += am / ad * rho16 / (1.0 - rho);
+        sdef += am * 1.4142135623730951 / (ad - h);
+        nfar += 1.0;
+    }
+    // Block sums: lanes by butterfly, then waves in index order (the bound covers any order).
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int n = 0; n < FAR_P; ++n) {
+            c1[n] += __shfl_xor(c1[n], off);
+            c2[n] += __shfl_xor(c2[n], off);
+        }
+        sfar += __shfl_xor(sfar, off);
+        trunc += __shfl_xor(trunc, off);
+        sdef += __shfl_xor(sdef, off);
+        nfar += __shfl_xor(nfar, off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int n = 0; n < FAR_P; ++n) {
+            sm.part[wave][n] = c1[n];
+            sm.part[wave][FAR_P + n] = c2[n];
+        }
+        sm.part[wave][2 * FAR_P] = sfar;
+        sm.part[wave][2 * FAR_P + 1] = trunc;
+        sm.part[wave][2 * FAR_P + 2] = sdef;
+        sm.part[wave][2 * FAR_P + 3] = nfar;
+    }
+    __syncthreads();
+    if (tid < 2 * FAR_P + 4) {
+        double v = 0.0;
+        for (int w = 0; w < FAR_THREADS / 64; ++w) v += sm.part[w][tid];
+        sm.coef[tid] = v;
+    }
+    __syncthreads();
+    const double SFAR = sm.coef[2 * FAR_P], TRUNC = sm.coef[2 * FAR_P + 1], SDEF = sm.coef[2 * FAR_P + 2];
+    const double NFAR = sm.coef[2 * FAR_P + 3];
+    const int n_near_all = sm.near_count;
+    const bool all_flagged = n_near_all > NEAR_EXP;
+    const int n_near = all_flagged ? 0 : n_near_all;
+    // Our own error from the far field (truncation + coefficient and evaluation rounding).
+    const double far_err = TRUNC + (NFAR + 16.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR;
+    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
+
+    // Phase 2: every ray of the patch; thread t owns column t % 64 and rows t / 64 + 4 r.
+    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
+    const int64_t W = a.i1 - a.i0;
+    const int lx = tid % PATCH_X, ly0 = tid / PATCH_X;
+#pragma unroll 1
+    for (int r = 0; r < FAR_ROWS; ++r) {
+        const int64_t i = ib + lx, j = jb + ly0 + r * (FAR_THREADS / PATCH_X);
+        const bool valid = (i < a.i1) && (j < a.jc1);
+        const double x1 = ray_coord(a.sx0, i, a.spx);
+        const double x2 = ray_coord(a.sy0, j, a.spy);
+        const double nw1 = ox - x1, nw2 = oy - x2;   // -w
+        double S1 = sm.coef[FAR_P - 1], S2 = sm.coef[2 * FAR_P - 1];
+#pragma unroll
+        for (int n = FAR_P - 2; n >= 0; --n) {
+            const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, sm.coef[n]));
+            const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, sm.coef[FAR_P + n]));
+            S1 = q1;
+            S2 = q2;
+        }
+        double a1 = S1, a2 = -S2;
+        double snear = 0.0;
+        bool tiny = false;
+        for (int q = 0; q < n_near; ++q) {
+            const double e1 = x1 - sm.near_x[q], e2 = x2 - sm.near_y[q];
+            const double r2 = __builtin_fma(e1, e1, e2 * e2);
+            tiny |= !(r2 > 1e-200);
+            const double f = sm.near_m[q] * rcp64(r2);
+            a1 = __builtin_fma(f, e1, a1);
+            a2 = __builtin_fma(f, e2, a2);
+            snear = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), snear);
+        }
+        const double y1 = a.c1 * x1 - a1;
+        const double y2 = a.c2 * x2 - a2;
+        const double u = (y1 - a.tx0) * a.inv_pixw;
+        const double v = (y2 - a.ty0) * a.inv_pixh;
+        // Error bound in source units: ours (far field + near sum + epilogue) and the
+        // definition's own rounding (lens-order FP64 sum over every lens, epilogue).
+        // near terms (stage-A style) and their additions onto the far-field sum
+        const double near_err = ((double)n_near + 10.0) * U64 * 1.001 * snear + (double)n_near * U64 * 1.34 * SFAR;
+        const double def_sum = kN * (snear + SDEF);
+        const double eu = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c1 * x1) + fabs(a1) + fabs(a.tx0));
+        const double ev = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c2 * x2) + fabs(a2) + fabs(a.ty0));
+        const double Mu = 1.001 * eu * a.inv_pixw, Mv = 1.001 * ev * a.inv_pixh;
+        const double fu = floor(u), fv = floor(v);
+        const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
+        const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
+        const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
+        const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
+        const bool sane = !tiny && !all_flagged && isfinite(Mu) && isfinite(Mv) && isfinite(u) && isfinite(v);
+        int code;
+        if (sane && ok_u && ok_v) code = (int)((int64_t)fv * a.npx + (int64_t)fu);
+        else if (sane && (out_u || out_v)) code = OUT;
+        else code = FLAGGED;
+        if (!valid) code = INT32_MIN;
+
+        n_in += __builtin_popcountll(__ballot(code >= 0));
+        n_out += __builtin_popcountll(__ballot(code == OUT));
+        if (PIX) {
+            if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+        } else {
+            aggregated_add(a.map, code);
+        }
+        const uint64_t fl = __ballot(code == FLAGGED);
+        if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
+    }
+    if (lane == 0) {
+        if (n_in) atomicAdd(a.counters + C_IN, n_in);
+        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
+        if (n_sing) atomicAdd(a.counters + C_SING, n_sing);
+    }
+}
+
 // Single map: one block per patch of this launch's rows.
 template <int RX, int RY, int WX, int WY, bool UNIT, int MODE, bool PIX>
 __global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) {
@@ -830,6 +1043,23 @@ hipError_t launch_shoot(const ShootArgs &a, int mode, int shape, hipStream_t str
         case 2: launch_shape<8, 2, 1, 2>(a, mode, grid, stream); break;
         case 3: launch_shape<8, 4, 1, 1>(a, mode, grid, stream); break;
         default: launch_shape<4, 2, 2, 2>(a, mode, grid, stream); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
+    const int64_t rows = a.jc1 - a.jc0;
+    const int64_t patches = a.nbx * ((rows + PATCH_Y - 1) / PATCH_Y);
+    if (patches <= 0) return hipSuccess;
+    const bool unit = a.lens_m == nullptr;
+    const bool pix = a.pix_out != nullptr;
+    const dim3 grid((unsigned)patches), block(FAR_THREADS);
+    if (unit) {
+        if (pix) hipLaunchKernelGGL((farfield_kernel<true, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((farfield_kernel<true, false>), grid, block, 0, stream, a);
+    } else {
+        if (pix) hipLaunchKernelGGL((farfield_kernel<false, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((farfield_kernel<false, false>), grid, block, 0, stream, a);
     }
     return hipGetLastError();
 }

@@ -59,6 +59,7 @@ int rs_tune(const rs_map_params *params, const double *lens_xy, const double *le
             rs_tune_result *result_host) {
     if (!params || !result_host || !scratch_map) return fail(RS_EINVAL, "NULL argument");
     if (params->flags & RS_RANDOM_RAYS) return fail(RS_EINVAL, "the tuner times regular-grid maps only");
+    if (params->mode == RS_FARFIELD) return fail(RS_EINVAL, "the tuner times the direct kernels only");
     rs_map_params p = *params;
     p.flags &= ~RS_ACCUMULATE;
     const int64_t W = p.i1 - p.i0, H = p.j1 - p.j0;

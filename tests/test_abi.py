@@ -147,3 +147,18 @@ def test_random_rays_flag_validation(lib):
     ws = 1 << 22
     assert lib.rs_make_maps(ctypes.byref(req), 1, ws, 1 << 40, None) == L.RS_EINVAL
     assert b"random rays" in lib.rs_last_error()
+
+
+def test_farfield_mode_validation(lib):
+    from paper_1005_5198_amd import _lib as L, api, workloads as w
+    s = w.config0()
+    c = api.to_params(s.params, "farfield")
+    assert c.mode == L.RS_FARFIELD
+    # it needs the re-check queue, like the mixed mode
+    assert lib.rs_workspace_bytes(ctypes.byref(c), s.n_lens) == api.workspace_bytes(s.params, s.n_lens, "mixed")
+    p = dict(s.params)
+    p.update(random_rays=1)
+    assert lib.rs_workspace_bytes(ctypes.byref(api.to_params(p, "farfield")), s.n_lens) == 0
+    assert b"regular grid" in lib.rs_last_error()
+    req = L.MapRequest(c, 1 << 20, None, s.n_lens, 1 << 21)
+    assert lib.rs_make_maps(ctypes.byref(req), 1, 1 << 22, 1 << 40, None) == L.RS_EINVAL
