@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the request loop vs one-at-a-time")
     ap.add_argument("--no-stats", action="store_true", help="skip the map-comparison statistics timing")
     ap.add_argument("--no-farfield", action="store_true", help="skip the far-field expansion mode timing")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default thread shape (skip the autotuner)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-rho", type=float, default=0.8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -116,6 +117,9 @@ def main():
     xy, m = rs.lens_tensors(spec.lens_xy, spec.lens_m)
     ws = rs.new_workspace(spec.params, spec.n_lens, args.mode)
     out = torch.empty((spec.params["npy"], spec.params["npx"]), dtype=torch.uint32, device="cuda")
+    tuned = None
+    if not args.no_tune:   # untimed: the autotuner times each thread shape on a band of the map
+        tuned = rs.tune(spec.params, xy, m, mode=args.mode)
 
     for _ in range(args.warmup):
         rs.make_map(spec.params, xy, m, mode=args.mode, out=out, workspace=ws)
@@ -163,6 +167,7 @@ def main():
                      "traffic": TRAFFIC_BYTES_PER_LAUNCH,
                      "kernel": "shoot_kernel (deflection + binning)",
                      "launches": launches, "mean_launch_ms": kernel_ms / max(launches, 1)},
+        "thread_shape": None if tuned is None else tuned["shapes"][tuned["best"]]["rays_per_lane"],
     }
     if args.mode == "mixed":
         # the plain-FP32 mode on the same map, for comparison

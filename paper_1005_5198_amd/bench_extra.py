@@ -167,7 +167,34 @@ def map_stats(rs, side: int = 4096, n_rays_a: float = 500.0, n_rays_b: float = 1
             "rms_dm": res["rms_dm"], "ks_d": res["ks_d"], "ks_p": res["ks_p"]}
 
 
-def phi_fiducial(rs, rows: int = 64, full: bool = False, band_rows: int = 2400, mode: str = "mixed") -> dict:
+def phi_fiducial_both(rs, band_rows: int = 2400) -> dict:
+    """The whole Phi_fiducial map twice: in far-field mode (one call), then with the direct
+    kernel band by band (about 8 minutes, one progress line per band on stderr); the two
+    count maps are compared pixel for pixel."""
+    import sys
+    spec = w.phi_fiducial()
+    p = spec.params
+    xy, _ = rs.lens_tensors(spec.lens_xy)
+    ff = torch.zeros((p["npy"], p["npx"]), dtype=torch.uint32, device="cuda")
+    ws = rs.new_workspace(p, spec.n_lens, "farfield")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs.make_map(p, xy, None, mode="farfield", out=ff, workspace=ws)
+    torch.cuda.synchronize()
+    t_ff = time.perf_counter() - t
+    st_ff = rs.read_stats(ws)
+    print(f"phi_fiducial far field: {t_ff:.2f} s", file=sys.stderr, flush=True)
+    r = phi_fiducial(rs, full=True, band_rows=band_rows, mode="mixed", out_map=True)
+    direct = r.pop("map")
+    diff = int((direct != ff).sum().item())
+    r.update({"farfield_seconds": t_ff, "farfield_rate_direct_equivalent": spec.interactions / t_ff,
+              "farfield_recheck_fraction": st_ff["rays_rechecked"] / spec.n_rays,
+              "pixels_differing": diff, "maps_equal": diff == 0})
+    return r
+
+
+def phi_fiducial(rs, rows: int = 64, full: bool = False, band_rows: int = 2400, mode: str = "mixed",
+                 out_map: bool = False) -> dict:
     """The 1e6-lens, 2500^2-pixel, 3.1e15-interaction map of Section 3.1's Phi_fiducial.
 
     By default a band of `rows` ray rows through the middle of the map is timed
@@ -212,11 +239,14 @@ def phi_fiducial(rs, rows: int = 64, full: bool = False, band_rows: int = 2400, 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     rate = spec.interactions / dt
-    return {"workload": spec.name, "rows": ny, "rays": spec.n_rays, "lenses": spec.n_lens,
-            "interactions": spec.interactions, "seconds": dt, "rate": rate,
-            "pct_fp32_peak": 10.0 * rate / 157.3e12, "recheck_fraction": total["rays_rechecked"] / spec.n_rays,
-            "rays_in_map": total["rays_in_map"], "rays_out": total["rays_out"],
-            "map_sum": int(out.to(torch.int64).sum().item())}
+    res = {"workload": spec.name, "rows": ny, "rays": spec.n_rays, "lenses": spec.n_lens,
+           "interactions": spec.interactions, "seconds": dt, "rate": rate,
+           "pct_fp32_peak": 10.0 * rate / 157.3e12, "recheck_fraction": total["rays_rechecked"] / spec.n_rays,
+           "rays_in_map": total["rays_in_map"], "rays_out": total["rays_out"],
+           "map_sum": int(out.to(torch.int64).sum().item())}
+    if out_map:
+        res["map"] = out
+    return res
 
 
 def far_field(rs, reps: int = 5) -> dict:
@@ -225,7 +255,7 @@ def far_field(rs, reps: int = 5) -> dict:
     second, and whether the map equals the mixed (direct) mode's, bit for bit."""
     spec = w.config2()
     xy, _ = rs.lens_tensors(spec.lens_xy)
-    ws = rs.new_workspace(spec.params, spec.n_lens, "mixed")
+    ws = rs.new_workspace(spec.params, spec.n_lens, "farfield")   # holds the mixed mode's needs too
     out = torch.empty((spec.params["npy"], spec.params["npx"]), dtype=torch.uint32, device="cuda")
     ref = rs.make_map(spec.params, xy, None, mode="mixed", workspace=ws).clone()
     rs.make_map(spec.params, xy, None, mode="farfield", out=out, workspace=ws)

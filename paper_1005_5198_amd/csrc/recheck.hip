@@ -48,6 +48,11 @@ __device__ inline void place(const RecheckArgs &a, int64_t i, int64_t j, int cod
 
 // ----------------------------- single map ---------------------------------
 
+// Below this many queued rays stage A runs one wave per ray (latency: a few
+// rays must not each take a thread through every lens); above it, one thread
+// per ray (throughput). Each of the two kernels checks the count on the device.
+constexpr uint32_t WAVE_STAGE_MAX = 32768;
+
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_exact_kernel(const RecheckArgs a) {
     const uint32_t n = *a.qcount;
@@ -69,6 +74,8 @@ __global__ __launch_bounds__(256) void recheck_exact_kernel(const RecheckArgs a)
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) {
     const uint32_t n = *a.qcount;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
+    if (n < WAVE_STAGE_MAX) return;   // recheck_fast_wave_kernel takes short queues
     const int64_t W = a.i1 - a.i0;
     unsigned long long n_in = 0, n_out = 0, n_sing = 0;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -85,7 +92,34 @@ __global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) 
         }
     }
     count_wave(a.counters, n_in, n_out, n_sing);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
+}
+
+// Stage A for a short queue: one wave per queued ray, rays dealt to the waves in turn.
+template <bool UNIT>
+__global__ __launch_bounds__(256) void recheck_fast_wave_kernel(const RecheckArgs a) {
+    const uint32_t n = *a.qcount;
+    if (n >= WAVE_STAGE_MAX) return;
+    const int64_t W = a.i1 - a.i0;
+    const int lane = __lane_id();
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    unsigned long long n_in = 0, n_out = 0, n_sing = 0;
+    for (uint32_t idx = wave_id; idx < n; idx += n_waves) {
+        const uint32_t q = a.queue[idx];
+        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
+        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
+        int code = 0;
+        const bool decided = fast_ray_wave<UNIT>(a, i, j, code);
+        if (lane == 0) {
+            if (decided) {
+                tally(code, n_in, n_out, n_sing);
+                place(a, i, j, code);
+            } else {
+                a.queue[idx] = q | UNRESOLVED;
+            }
+        }
+    }
+    count_wave(a.counters, n_in, n_out, n_sing);
 }
 
 template <bool UNIT>
@@ -95,10 +129,13 @@ __global__ __launch_bounds__(256) void recheck_exact_wave_kernel(const RecheckAr
     const int lane = __lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t base = wave_id * 64u; base < n; base += n_waves * 64u) {
-        const uint32_t idx = base + (uint32_t)lane;
-        const uint32_t q_lane = idx < n ? a.queue[idx] : 0u;
-        uint64_t todo = __ballot(idx < n && (q_lane & UNRESOLVED));
+    // Entries are dealt to the waves one at a time (entry wave_id + t * n_waves), so
+    // neighbouring marked rays go to different waves instead of queueing in one.
+    for (uint64_t t0 = 0; (uint64_t)wave_id + t0 * n_waves < n; t0 += 64) {
+        const uint64_t idx64 = (uint64_t)wave_id + (t0 + (uint64_t)lane) * n_waves;
+        const uint32_t idx = (uint32_t)(idx64 < n ? idx64 : 0);
+        const uint32_t q_lane = idx64 < n ? a.queue[idx] : 0u;
+        uint64_t todo = __ballot(idx64 < n && (q_lane & UNRESOLVED));
         while (todo) {
             const int src = __builtin_ctzll(todo);
             todo &= todo - 1;
@@ -250,9 +287,11 @@ hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_onl
         else hipLaunchKernelGGL(recheck_exact_kernel<false>, grid, block, 0, stream, a);
     } else if (unit) {
         hipLaunchKernelGGL(recheck_fast_kernel<true>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL(recheck_fast_wave_kernel<true>, grid, block, 0, stream, a);
         hipLaunchKernelGGL(recheck_exact_wave_kernel<true>, grid, block, 0, stream, a);
     } else {
         hipLaunchKernelGGL(recheck_fast_kernel<false>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL(recheck_fast_wave_kernel<false>, grid, block, 0, stream, a);
         hipLaunchKernelGGL(recheck_exact_wave_kernel<false>, grid, block, 0, stream, a);
     }
     return hipGetLastError();

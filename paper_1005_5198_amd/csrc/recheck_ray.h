@@ -173,6 +173,65 @@ __device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int 
     return false;
 }
 
+// Stage A by a whole wave for one ray (i, j wave-uniform): lanes take every 64th
+// lens, then the partial sums meet in a fixed butterfly. Any summation order
+// stays within the same bound, (N + 10) 2^-53 S, so the decision rule is
+// fast_ray's. Every lane returns the same result.
+template <bool UNIT>
+__device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
+    const double U64 = 1.1102230246251565e-16;  // 2^-53
+    double x1, x2;
+    ray_xy(a, i, j, x1, x2);
+    const double c1 = (1.0 - a.gamma) - a.sigma_c;
+    const double c2 = (1.0 + a.gamma) - a.sigma_c;
+    const double inv_pixw = (double)a.npx / a.tw;
+    const double inv_pixh = (double)a.npy / a.th;
+    double a1 = 0.0, a2 = 0.0, S = 0.0;
+    int tiny = 0;
+    for (int64_t k = __lane_id(); k < a.n_lens; k += 64) {
+        const double d1 = x1 - a.lens_xy[2 * k];
+        const double d2 = x2 - a.lens_xy[2 * k + 1];
+        const double r2 = __builtin_fma(d1, d1, d2 * d2);
+        tiny |= !(r2 > 1e-200);
+        double rc = __builtin_amdgcn_rcp(r2);
+        double e = __builtin_fma(-r2, rc, 1.0);
+        rc = __builtin_fma(rc, e, rc);
+        e = __builtin_fma(-r2, rc, 1.0);
+        rc = __builtin_fma(rc, e, rc);
+        if (!UNIT) rc = rc * a.lens_m[k];
+        a1 = __builtin_fma(d1, rc, a1);
+        a2 = __builtin_fma(d2, rc, a2);
+        S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a1 += __shfl_xor(a1, off);
+        a2 += __shfl_xor(a2, off);
+        S += __shfl_xor(S, off);
+        tiny |= __shfl_xor(tiny, off);
+    }
+    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
+    const double u = (c1 * x1 - a1 - a.tx0) * inv_pixw;
+    const double v = (c2 * x2 - a2 - a.ty0) * inv_pixh;
+    const double Mu = 2.002 * (kN * S + 8.0 * U64 * (fabs(c1 * x1) + fabs(a1) + fabs(a.tx0))) * inv_pixw;
+    const double Mv = 2.002 * (kN * S + 8.0 * U64 * (fabs(c2 * x2) + fabs(a2) + fabs(a.ty0))) * inv_pixh;
+    const double fu = floor(u), fv = floor(v);
+    const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
+    const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
+    const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
+    const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
+    const bool sane = !tiny && isfinite(S) && isfinite(Mu) && isfinite(Mv);
+    if (sane && ok_u && ok_v) {
+        code = (int)((int64_t)fv * a.npx + (int64_t)fu);
+        return true;
+    }
+    if (sane && (out_u || out_v)) {
+        code = CODE_OUT;
+        return true;
+    }
+    return false;
+}
+
 // Bin one re-checked ray (or write its pixel) and count it in the map's counters.
 __device__ inline void emit_ray(const RecheckArgs &a, int64_t i, int64_t j, int code) {
     if (a.pix_out) {

@@ -74,7 +74,16 @@ struct ShootArgs {
     uint32_t *bin_cursor;  // [n_bins] scatter cursors
     uint32_t *ray_rel;     // [rays] chunk-relative index (j - jc0) * (i1 - i0) + (i - i0), by bin
     double *ray_x, *ray_y; // [rays] FP64 positions, same order
+    // Far-field expansion (RS_FARFIELD): super-patches of FF_SP_X x FF_SP_Y patches.
+    int64_t ff_sbx;        // super-patches along x in this launch
+    double *ff_super;      // [n_super][2 * 16 + 4] coefficients and bound terms
+    int32_t *ff_near;      // [n_super][1 + FF_NEAR_CAP] count, then indices of the nearer lenses
 };
+
+constexpr int FF_SP_X = 4;
+constexpr int FF_SP_Y = 4;
+constexpr int FF_NEAR_CAP = 4096;
+constexpr int FF_REC_DOUBLES = 36;
 
 // Random rays: expected rays per bin (a block's capacity is 2048, so a bin
 // overflows it only beyond seven standard deviations, and then takes a second

@@ -41,6 +41,9 @@ struct Plan {
     int64_t bins_cap = 0, rays_cap = 0;
     size_t bin_count_off = 0, bin_offset_off = 0, bin_cursor_off = 0;
     size_t rel_off = 0, x_off = 0, y_off = 0;
+    // Far-field expansion: super-patch records and lens lists for the largest launch.
+    int64_t super_cap = 0;
+    size_t ff_super_off = 0, ff_near_off = 0;
     size_t bytes = 0;
 };
 
@@ -102,6 +105,17 @@ Plan make_plan(const rs_map_params *p) {
     pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
     pl.qcount_bytes = (WS_QCOUNT + 4 * (size_t)pl.n_chunks + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
+    if (p->mode == RS_FARFIELD && pl.n_chunks > 0) {
+        const int64_t nbx = (pl.W + PATCH_X - 1) / PATCH_X;
+        const int64_t nby = (rows_cap + PATCH_Y - 1) / PATCH_Y;
+        pl.super_cap = ((nbx + FF_SP_X - 1) / FF_SP_X) * ((nby + FF_SP_Y - 1) / FF_SP_Y);
+        size_t off = a256(pl.bytes);
+        pl.ff_super_off = off;
+        off += a256(sizeof(double) * FF_REC_DOUBLES * (size_t)pl.super_cap);
+        pl.ff_near_off = off;
+        off += a256(sizeof(int32_t) * (1 + (size_t)FF_NEAR_CAP) * (size_t)pl.super_cap);
+        pl.bytes = off;
+    }
     if (pl.random && pl.n_chunks > 0) {
         pl.rays_cap = rows_cap * pl.W;
         const int64_t last_rows = pl.H - (pl.n_chunks - 1) * rows;
@@ -278,6 +292,9 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
             a.inv_bh = (double)a.nby_r / p->sh;
             e = launch_shoot_random(a, p->mode, stream);
         } else if (p->mode == RS_FARFIELD) {
+            a.ff_sbx = (a.nbx + FF_SP_X - 1) / FF_SP_X;
+            a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
+            a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
             e = launch_farfield(a, stream);
         } else {
             e = launch_shoot(a, p->mode, shape, stream);

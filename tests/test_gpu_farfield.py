@@ -90,7 +90,7 @@ def test_farfield_config2_full_equals_mixed(rs):
     oracle's, see the parity tests), and sampled rays equal the oracle's one by one."""
     s = w.config2()
     xy, _ = rs.lens_tensors(s.lens_xy)
-    ws = rs.new_workspace(s.params, s.n_lens, "mixed")
+    ws = rs.new_workspace(s.params, s.n_lens, "farfield")   # holds the mixed mode's needs too
     mixed = rs.make_map(s.params, xy, None, mode="mixed", workspace=ws)
     ff = rs.make_map(s.params, xy, None, mode="farfield", workspace=ws)
     st = rs.read_stats(ws)
