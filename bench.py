@@ -36,10 +36,10 @@ FP32_PEAK_TFLOPS = 157.3       # 256 CU x 2.4 GHz x 128 FP32 lanes x 2 FLOP (FMA
 FLOP_PER_INTERACTION = 10      # the paper's N_FLOP (Section 2, Phi); one deflection term
 METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batched vs plain"
 
-# HBM traffic of the deflection kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on the
-# same workload, scaled by the copy-kernel calibration factor. None until measured for the
-# current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# HBM bytes per launch of the mixed-mode deflection kernel on this workload: rocprofv3 --pmc
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB copy), measured on the current
+# kernel (profiles/shoot_kernel_config2.md). Set to None whenever the kernel changes.
+TRAFFIC_BYTES_PER_LAUNCH = 1.044e9
 
 
 def parse():
@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-stats", action="store_true", help="skip the map-comparison statistics timing")
     ap.add_argument("--no-farfield", action="store_true", help="skip the far-field expansion mode timing")
     ap.add_argument("--no-tune", action="store_true", help="keep the default thread shape (skip the autotuner)")
+    ap.add_argument("--no-random", action="store_true", help="skip the random-ray map timing")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-rho", type=float, default=0.8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -180,7 +181,7 @@ def main():
             rs.make_map(spec.params, xy, m, mode="fp32", out=out, workspace=ws32)
         torch.cuda.synchronize()
         result["fp32_mode_value"] = inter * n32 / (time.perf_counter() - t)
-    if not (args.no_batched and args.no_serve and args.no_stats and args.no_farfield):
+    if not (args.no_batched and args.no_serve and args.no_stats and args.no_farfield and args.no_random):
         from paper_1005_5198_amd import bench_extra
         if not args.no_batched:
             result["batched"] = bench_extra.batched(rs, mode=args.mode)
@@ -191,6 +192,8 @@ def main():
             result["map_stats"] = bench_extra.map_stats(rs)
         if not args.no_farfield:
             result["far_field"] = bench_extra.far_field(rs)
+        if not args.no_random:
+            result["random_rays"] = bench_extra.random_rays(rs, mode=args.mode)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(result), flush=True)

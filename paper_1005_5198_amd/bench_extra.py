@@ -270,3 +270,24 @@ def far_field(rs, reps: int = 5) -> dict:
             "direct_equivalent_interactions_per_s": spec.interactions / dt,
             "recheck_fraction": st["rays_rechecked"] / spec.n_rays,
             "equals_mixed_map": bool(torch.equal(out, ref))}
+
+
+def random_rays(rs, reps: int = 3, mode: str = "mixed") -> dict:
+    """The config-2 map with Philox-random ray positions (the paper's GPU code's sampling):
+    time per map and interactions/s against the regular grid's, plus the re-check fraction."""
+    spec = w.config2()
+    p = dict(spec.params)
+    p.update(random_rays=1, seed=2)
+    xy, _ = rs.lens_tensors(spec.lens_xy)
+    ws = rs.new_workspace(p, spec.n_lens, mode)
+    out = torch.empty((p["npy"], p["npx"]), dtype=torch.uint32, device="cuda")
+    rs.make_map(p, xy, None, mode=mode, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        rs.make_map(p, xy, None, mode=mode, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    st = rs.read_stats(ws)
+    return {"workload": "config2, random rays", "mode": mode, "ms_per_map": dt * 1e3,
+            "interactions_per_s": spec.interactions / dt, "recheck_fraction": st["rays_rechecked"] / spec.n_rays}
