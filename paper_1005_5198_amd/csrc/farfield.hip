@@ -1,0 +1,371 @@
+// Far-field expansion (RS_FARFIELD): two levels of FP64 local expansions of the
+// distant lenses, near lenses summed directly, a rigorous per-ray bound.
+#include "shoot_common.h"
+
+namespace rs {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Far-field expansion (RS_FARFIELD). The paper's tree codes group distant
+// lenses into pseudo-lenses with higher multipoles (Section 2, Eq.
+// (hierarchical)); here distant lenses enter local expansions of the
+// deflection, to order FAR_P, on two levels:
+//   * super-patch (FF_SP_X x FF_SP_Y patches, centre zS, half-diagonal H):
+//     lenses farther than FAR_RATIO H give C_n = sum_k m_k tS_k^(n+1),
+//     tS_k = 1 / (zS - z_k); nearer lenses go to the super-patch's list;
+//   * patch (64 x 32 rays, centre z0, half-diagonal h): the super expansion
+//     is re-centred exactly on z0 (a polynomial translation), and the listed
+//     lenses farther than FAR_RATIO h from z0 add c_n = sum_k m_k t_k^(n+1),
+//     t_k = 1 / (z0 - z_k); the rest are summed directly.
+// With z = x1 + i x2 and w = z - z0, sum_k m_k / (z - z_k) = sum_n (-w)^n T_n,
+// and the deflection (a1, a2) is (Re, -Im) of that sum. All of it is FP64; each
+// ray carries a rigorous bound (series truncation on both levels, rounding of
+// the coefficients, the translation and the evaluation, the near sum) plus the
+// definition's own rounding, and rays within it of a pixel edge go to the FP64
+// re-check, so the map equals the definition's.
+// ---------------------------------------------------------------------------
+constexpr int FAR_P = 16;
+constexpr double FAR_RATIO = 4.0;
+constexpr int FAR_THREADS = 256;
+constexpr int FAR_ROWS = PATCH_X * PATCH_Y / FAR_THREADS;     // rays per thread (8)
+static_assert(FAR_ROWS * (FAR_THREADS / 64) == (PATCH_X / 8) * (PATCH_Y / 8), "8 x 8 blocks cover the patch");
+constexpr int NEAR_EXP = 512;
+constexpr int FAR_EXTRA = 4;                                    // SFAR, TRUNC, SDEF, NFAR
+constexpr int FAR_REC = 2 * FAR_P + FAR_EXTRA;
+static_assert(FAR_REC == FF_REC_DOUBLES, "super-patch record size");
+
+__device__ __forceinline__ double rcp64(double r2) {
+    double rc = __builtin_amdgcn_rcp(r2);
+    double e = __builtin_fma(-r2, rc, 1.0);
+    rc = __builtin_fma(rc, e, rc);
+    e = __builtin_fma(-r2, rc, 1.0);
+    return __builtin_fma(rc, e, rc);
+}
+
+// One lens's contribution to an expansion about (ox, oy) with half-diagonal h
+// (the lens is at least FAR_RATIO h away): the powers m t^(n+1) and the bound
+// terms m/|d|, m/|d| rho^P / (1 - rho) and sqrt(2) m / (|d| - h).
+struct FarAcc {
+    double c1[FAR_P], c2[FAR_P];
+    double sfar, trunc, sdef, nfar;
+    __device__ void zero() {
+#pragma unroll
+        for (int n = 0; n < FAR_P; ++n) {
+            c1[n] = 0.0;
+            c2[n] = 0.0;
+        }
+        sfar = trunc = sdef = nfar = 0.0;
+    }
+    __device__ __forceinline__ void add(double d1, double d2, double r2, double m, double h) {
+        const double inv = rcp64(r2);
+        const double t1 = d1 * inv, t2 = -d2 * inv;   // t = 1 / d, d = centre - lens
+        double p1 = m * t1, p2 = m * t2;
+        c1[0] += p1;
+        c2[0] += p2;
+#pragma unroll
+        for (int n = 1; n < FAR_P; ++n) {
+            const double q1 = __builtin_fma(p1, t1, -p2 * t2);
+            const double q2 = __builtin_fma(p1, t2, p2 * t1);
+            p1 = q1;
+            p2 = q2;
+            c1[n] += p1;
+            c2[n] += p2;
+        }
+        const double ad = sqrt(r2);
+        const double am = fabs(m);
+        const double rho = h / ad;
+        const double rho2 = rho * rho, rho4 = rho2 * rho2, rho8 = rho4 * rho4, rho16 = rho8 * rho8;
+        sfar += am / ad;
+        trunc += am / ad * rho16 / (1.0 - rho);
+        sdef += am * 1.4142135623730951 / (ad - h);
+        nfar += 1.0;
+    }
+    // Block sum into out[FAR_REC] (shared); lanes by butterfly, then waves in index order.
+    __device__ void reduce(double (*part)[FAR_REC], double *out) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int n = 0; n < FAR_P; ++n) {
+                c1[n] += __shfl_xor(c1[n], off);
+                c2[n] += __shfl_xor(c2[n], off);
+            }
+            sfar += __shfl_xor(sfar, off);
+            trunc += __shfl_xor(trunc, off);
+            sdef += __shfl_xor(sdef, off);
+            nfar += __shfl_xor(nfar, off);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int n = 0; n < FAR_P; ++n) {
+                part[wave][n] = c1[n];
+                part[wave][FAR_P + n] = c2[n];
+            }
+            part[wave][2 * FAR_P] = sfar;
+            part[wave][2 * FAR_P + 1] = trunc;
+            part[wave][2 * FAR_P + 2] = sdef;
+            part[wave][2 * FAR_P + 3] = nfar;
+        }
+        __syncthreads();
+        if (threadIdx.x < FAR_REC) {
+            double v = 0.0;
+            for (int w = 0; w < FAR_THREADS / 64; ++w) v += part[w][threadIdx.x];
+            out[threadIdx.x] = v;
+        }
+        __syncthreads();
+    }
+};
+
+// Geometry of super-patch sp of this launch: centre and half-diagonal (one ray
+// spacing of slack on each side), of the full box even where the window clips it.
+__device__ __forceinline__ void super_geometry(const ShootArgs &a, int64_t sp, double &cx, double &cy, double &H) {
+    const int64_t sx = sp % a.ff_sbx, sy = sp / a.ff_sbx;
+    const int64_t i_s = a.i0 + sx * (FF_SP_X * PATCH_X);
+    const int64_t j_s = a.jc0 + sy * (FF_SP_Y * PATCH_Y);
+    cx = a.sx0 + ((double)i_s + 0.5 * (FF_SP_X * PATCH_X)) * a.spx;
+    cy = a.sy0 + ((double)j_s + 0.5 * (FF_SP_Y * PATCH_Y)) * a.spy;
+    const double hx = (0.5 * (FF_SP_X * PATCH_X) + 1.0) * a.spx;
+    const double hy = (0.5 * (FF_SP_Y * PATCH_Y) + 1.0) * a.spy;
+    H = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
+}
+
+struct FarSuperSmem {
+    double part[FAR_THREADS / 64][FAR_REC];
+    double out[FAR_REC];
+    int count;
+};
+
+// Level 1: one block per super-patch. Far lenses -> coefficients C about zS;
+// the others -> the super-patch's lens list (a count above FF_NEAR_CAP means
+// the list is incomplete and the patches scan every lens instead).
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const ShootArgs a) {
+    __shared__ FarSuperSmem sm;
+    const int64_t sp = blockIdx.x;
+    double cx, cy, H;
+    super_geometry(a, sp, cx, cy, H);
+    const double near_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
+    int32_t *list = a.ff_near + sp * (int64_t)(1 + FF_NEAR_CAP);
+    if (threadIdx.x == 0) sm.count = 0;
+    __syncthreads();
+    FarAcc acc;
+    acc.zero();
+    for (int64_t k = threadIdx.x; k < a.n_lens; k += FAR_THREADS) {
+        const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
+        const double d1 = cx - X, d2 = cy - Y;
+        const double r2 = d1 * d1 + d2 * d2;
+        if (!(r2 >= near_r2)) {
+            const int q = atomicAdd(&sm.count, 1);
+            if (q < FF_NEAR_CAP) list[1 + q] = (int32_t)k;
+            continue;
+        }
+        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
+        acc.add(d1, d2, r2, m, H);
+    }
+    acc.reduce(sm.part, sm.out);
+    double *rec = a.ff_super + sp * (int64_t)FAR_REC;
+    if (threadIdx.x < FAR_REC) rec[threadIdx.x] = sm.out[threadIdx.x];
+    if (threadIdx.x == 0) list[0] = sm.count;
+}
+
+struct FarSmem {
+    double near_x[NEAR_EXP], near_y[NEAR_EXP], near_m[NEAR_EXP];
+    int near_count;
+    double part[FAR_THREADS / 64][FAR_REC];
+    double pc[FAR_REC];          // this patch's own expansion (listed lenses)
+    double sc[FAR_REC];          // the super-patch's record
+    double tc[2 * FAR_P];        // total coefficients about z0
+};
+
+// Level 2: one block per patch.
+template <bool UNIT, bool PIX>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a) {
+    __shared__ FarSmem sm;
+    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t patch = blockIdx.x;
+    const int64_t pbx = patch % a.nbx, pby = patch / a.nbx;
+    const int64_t ib = a.i0 + pbx * PATCH_X;
+    const int64_t jb = a.jc0 + pby * PATCH_Y;
+    const double ox = a.sx0 + ((double)ib + 0.5 * PATCH_X) * a.spx;
+    const double oy = a.sy0 + ((double)jb + 0.5 * PATCH_Y) * a.spy;
+    const double hx = (0.5 * PATCH_X + 1.0) * a.spx;
+    const double hy = (0.5 * PATCH_Y + 1.0) * a.spy;
+    const double h = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
+    const double near_r2 = (FAR_RATIO * h) * (FAR_RATIO * h);
+    // This patch's super-patch.
+    const int64_t sp = (pby / FF_SP_Y) * a.ff_sbx + pbx / FF_SP_X;
+    double cx, cy, H;
+    super_geometry(a, sp, cx, cy, H);
+    const double super_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
+    const int32_t *list = a.ff_near + sp * (int64_t)(1 + FF_NEAR_CAP);
+    const int32_t listed = list[0];
+    const bool scan_all = listed > FF_NEAR_CAP;
+    if (tid == 0) sm.near_count = 0;
+    if (tid < FAR_REC) sm.sc[tid] = a.ff_super[sp * (int64_t)FAR_REC + tid];
+    __syncthreads();
+
+    // The super-patch's nearer lenses: far from this patch -> its own expansion; else direct.
+    FarAcc acc;
+    acc.zero();
+    const int64_t n_cand = scan_all ? a.n_lens : (int64_t)listed;
+    for (int64_t q = tid; q < n_cand; q += FAR_THREADS) {
+        const int64_t k = scan_all ? q : (int64_t)list[1 + q];
+        const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
+        if (scan_all) {   // the same test the super kernel made
+            const double e1 = cx - X, e2 = cy - Y;
+            if (e1 * e1 + e2 * e2 >= super_r2) continue;
+        }
+        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
+        const double d1 = ox - X, d2 = oy - Y;
+        const double r2 = d1 * d1 + d2 * d2;
+        if (!(r2 >= near_r2)) {
+            const int j = atomicAdd(&sm.near_count, 1);
+            if (j < NEAR_EXP) {
+                sm.near_x[j] = X;
+                sm.near_y[j] = Y;
+                sm.near_m[j] = m;
+            }
+            continue;
+        }
+        acc.add(d1, d2, r2, m, h);
+    }
+    acc.reduce(sm.part, sm.pc);
+
+    // Re-centre the super expansion: sum_n C_n (e + v)^n = sum_m v^m sum_{n>=m} binom(n,m) e^(n-m) C_n,
+    // v = -w = z0 - z, e = zS - z0; then add this patch's own coefficients.
+    if (tid < FAR_P) {
+        const int mm = tid;
+        const double e1 = cx - ox, e2 = cy - oy;
+        double s1 = 0.0, s2 = 0.0;
+        double g1 = 1.0, g2 = 0.0;   // e^(n-m)
+        double binom = 1.0;          // binom(n, m), exact in FP64 for n < 16
+        for (int n = mm; n < FAR_P; ++n) {
+            s1 = __builtin_fma(binom, g1 * sm.sc[n] - g2 * sm.sc[FAR_P + n], s1);
+            s2 = __builtin_fma(binom, g1 * sm.sc[FAR_P + n] + g2 * sm.sc[n], s2);
+            const double q1 = g1 * e1 - g2 * e2, q2 = g1 * e2 + g2 * e1;
+            g1 = q1;
+            g2 = q2;
+            binom = binom * (double)(n + 1) / (double)(n + 1 - mm);
+        }
+        sm.tc[mm] = s1 + sm.pc[mm];
+        sm.tc[FAR_P + mm] = s2 + sm.pc[FAR_P + mm];
+    }
+    __syncthreads();
+    const double SFAR_S = sm.sc[2 * FAR_P], TRUNC_S = sm.sc[2 * FAR_P + 1], SDEF_S = sm.sc[2 * FAR_P + 2];
+    const double NFAR_S = sm.sc[2 * FAR_P + 3];
+    const double SFAR_P = sm.pc[2 * FAR_P], TRUNC_P = sm.pc[2 * FAR_P + 1], SDEF_P = sm.pc[2 * FAR_P + 2];
+    const double NFAR_P = sm.pc[2 * FAR_P + 3];
+    const int n_near_all = sm.near_count;
+    const bool all_flagged = n_near_all > NEAR_EXP;
+    const int n_near = all_flagged ? 0 : n_near_all;
+    const double SFAR = SFAR_S + SFAR_P;
+    // Our own far-field error: truncation on both levels; rounding of the coefficients,
+    // the translation and the evaluation (per-level factors, generous constants).
+    const double far_err = TRUNC_S + TRUNC_P + (NFAR_S + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_S +
+                           (NFAR_P + 16.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_P;
+    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
+    const double SDEF = SDEF_S + SDEF_P;
+
+    unsigned long long n_in = 0, n_out = 0;
+    const int64_t W = a.i1 - a.i0;
+    // A wave takes 8 x 8-ray blocks of the patch (block wave + 4 r, r < 8), so the
+    // rays of one wave land on few pixels and the binning atomics aggregate well.
+    const int wave = tid >> 6;
+#pragma unroll 1
+    for (int r = 0; r < FAR_ROWS; ++r) {
+        const int b = wave + (FAR_THREADS / 64) * r;
+        const int64_t i = ib + 8 * (b % (PATCH_X / 8)) + (lane & 7);
+        const int64_t j = jb + 8 * (b / (PATCH_X / 8)) + (lane >> 3);
+        const bool valid = (i < a.i1) && (j < a.jc1);
+        const double x1 = ray_coord(a.sx0, i, a.spx);
+        const double x2 = ray_coord(a.sy0, j, a.spy);
+        const double nw1 = ox - x1, nw2 = oy - x2;   // -w
+        double S1 = sm.tc[FAR_P - 1], S2 = sm.tc[2 * FAR_P - 1];
+#pragma unroll
+        for (int n = FAR_P - 2; n >= 0; --n) {
+            const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, sm.tc[n]));
+            const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, sm.tc[FAR_P + n]));
+            S1 = q1;
+            S2 = q2;
+        }
+        double a1 = S1, a2 = -S2;
+        double snear = 0.0;
+        bool tiny = false;
+        for (int q = 0; q < n_near; ++q) {
+            const double e1 = x1 - sm.near_x[q], e2 = x2 - sm.near_y[q];
+            const double r2 = __builtin_fma(e1, e1, e2 * e2);
+            tiny |= !(r2 > 1e-200);
+            const double f = sm.near_m[q] * rcp64(r2);
+            a1 = __builtin_fma(f, e1, a1);
+            a2 = __builtin_fma(f, e2, a2);
+            snear = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), snear);
+        }
+        const double y1 = a.c1 * x1 - a1;
+        const double y2 = a.c2 * x2 - a2;
+        const double u = (y1 - a.tx0) * a.inv_pixw;
+        const double v = (y2 - a.ty0) * a.inv_pixh;
+        // Error bound in source units: ours (far field, near sum and its additions onto
+        // the far sum, epilogue) and the definition's own lens-order rounding.
+        const double near_err =
+            ((double)n_near + 10.0) * U64 * 1.001 * snear + (double)n_near * U64 * 1.34 * SFAR;
+        const double def_sum = kN * (snear + SDEF);
+        const double eu = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c1 * x1) + fabs(a1) + fabs(a.tx0));
+        const double ev = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c2 * x2) + fabs(a2) + fabs(a.ty0));
+        const double Mu = 1.001 * eu * a.inv_pixw, Mv = 1.001 * ev * a.inv_pixh;
+        const double fu = floor(u), fv = floor(v);
+        const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
+        const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
+        const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
+        const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
+        const bool sane = !tiny && !all_flagged && isfinite(Mu) && isfinite(Mv) && isfinite(u) && isfinite(v);
+        int code;
+        if (sane && ok_u && ok_v) code = (int)((int64_t)fv * a.npx + (int64_t)fu);
+        else if (sane && (out_u || out_v)) code = OUT;
+        else code = FLAGGED;
+        if (!valid) code = INT32_MIN;
+
+        n_in += __builtin_popcountll(__ballot(code >= 0));
+        n_out += __builtin_popcountll(__ballot(code == OUT));
+        if (PIX) {
+            if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+        } else {
+            aggregated_add(a.map, code);
+        }
+        const uint64_t fl = __ballot(code == FLAGGED);
+        if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
+    }
+    if (lane == 0) {
+        if (n_in) atomicAdd(a.counters + C_IN, n_in);
+        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
+    const int64_t rows = a.jc1 - a.jc0;
+    const int64_t nby = (rows + PATCH_Y - 1) / PATCH_Y;
+    const int64_t patches = a.nbx * nby;
+    if (patches <= 0) return hipSuccess;
+    const int64_t n_super = a.ff_sbx * ((nby + FF_SP_Y - 1) / FF_SP_Y);
+    const bool unit = a.lens_m == nullptr;
+    const bool pix = a.pix_out != nullptr;
+    const dim3 block(FAR_THREADS);
+    if (unit) hipLaunchKernelGGL((farfield_super_kernel<true>), dim3((unsigned)n_super), block, 0, stream, a);
+    else hipLaunchKernelGGL((farfield_super_kernel<false>), dim3((unsigned)n_super), block, 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)patches);
+    if (unit) {
+        if (pix) hipLaunchKernelGGL((farfield_kernel<true, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((farfield_kernel<true, false>), grid, block, 0, stream, a);
+    } else {
+        if (pix) hipLaunchKernelGGL((farfield_kernel<false, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((farfield_kernel<false, false>), grid, block, 0, stream, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rs

@@ -77,19 +77,22 @@ __device__ inline int exact_ray_thread(const RecheckArgs &a, int64_t i, int64_t 
     return CODE_OUT;
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // The same definition evaluated by a whole wave for one ray (i, j wave-uniform):
 // lanes form the per-lens terms (m/r2)*d1, (m/r2)*d2 of 64 lenses at a time and
-// the lens-order sum adds them one by one.
+// stage them in LDS; every lane then adds them in lens order (the same sum in
+// every lane, so no lane-to-scalar moves sit on the dependent chain). Callers
+// are blocks of at most 256 threads.
+__device__ __forceinline__ void wave_lds_fence() {
+    // LDS accesses of one wave complete in order; keep the compiler from moving them across.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <bool UNIT>
 __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j) {
+    __shared__ double terms[4][2][64];
     const int lane = __lane_id();
+    const int w = (threadIdx.x >> 6) & 3;
     double x1, x2;
     ray_xy(a, i, j, x1, x2);
     double a1 = 0.0, a2 = 0.0;
@@ -108,11 +111,16 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
             t2 = f * d2;
         }
         if (__ballot(zero)) return CODE_SINGULAR;
+        terms[w][0][lane] = t1;
+        terms[w][1][lane] = t2;
+        wave_lds_fence();
         const int cnt = (a.n_lens - k0) < 64 ? (int)(a.n_lens - k0) : 64;
+#pragma unroll 8
         for (int l = 0; l < cnt; ++l) {
-            a1 += readlane_f64(t1, l);
-            a2 += readlane_f64(t2, l);
+            a1 += terms[w][0][l];
+            a2 += terms[w][1][l];
         }
+        wave_lds_fence();   // every lane has read this chunk before the next one is written
     }
     const double y1 = ((1.0 - a.gamma) - a.sigma_c) * x1 - a1;
     const double y2 = ((1.0 + a.gamma) - a.sigma_c) * x2 - a2;
