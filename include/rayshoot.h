@@ -252,9 +252,10 @@ int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_ho
 /* A scheduler thread admits requests in arrival order when a slot is free and */
 /* their device footprint (lenses, masses, map) fits the server's pool, and    */
 /* keeps two launch steps in flight. Each step hands out about slice_ms of GPU  */
-/* work as bands of ray rows, least remaining work first (every active request */
-/* gets at least one 32-row band; one waiting longer than starve_s since its   */
-/* submission goes first), and runs them as one rs_make_maps batch. A          */
+/* work as bands of ray rows: requests waiting longer than starve_s since     */
+/* submission first (oldest first), then least remaining work first, in whole  */
+/* 32-row bands while the budget lasts (the first request always gets one),    */
+/* and runs them as one rs_make_maps batch. A                                  */
 /* request that arrives while the GPU is busy joins the next step; a small one */
 /* then finishes without waiting for large ones. Each finished map equals      */
 /* rs_make_map of the same request bit for bit (a map is the integer sum of its */

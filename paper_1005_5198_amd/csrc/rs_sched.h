@@ -142,8 +142,9 @@ class Policy {
     // (oldest first), then to the others in order of least remaining work,
     // discounted by age: remaining / (1 + waited / aging_s). A small request
     // finishes in the next step instead of queueing behind a large one, and a
-    // large one cannot be postponed past starve_s. Every open job gets at least
-    // one 32-row band per step.
+    // large one cannot be postponed past starve_s. Bands are whole multiples of
+    // 32 rows; the first job in that order always gets one, the others only
+    // while the budget lasts.
     std::vector<Slice> plan(double target_interactions, double now = 0.0, double aging_s = 0.25,
                             double starve_s = 0.5) {
         std::vector<Slice> step;
@@ -165,6 +166,9 @@ class Policy {
         });
         double left = target_interactions;
         for (Job *j : open) {
+            // The first job in priority order always gets at least one band (progress);
+            // the others share what is left of the budget, in whole bands.
+            if (!step.empty() && left < per_row(j) * (double)ROW_QUANTUM) continue;
             int64_t rows = left > 0 ? (int64_t)(left / per_row(j)) : 0;
             rows = std::max<int64_t>(ROW_QUANTUM, rows / ROW_QUANTUM * ROW_QUANTUM);
             const int64_t row1 = std::min(j->rows, j->next_row + rows);

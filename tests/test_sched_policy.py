@@ -45,8 +45,9 @@ def test_shortest_remaining_first(res):
 
 
 def test_starvation_guard(res):
-    # the big job has waited past starve_s: it takes the budget (128 rows), the small one a band
-    assert res["starve_step1"] == [[1, 0, 128], [2, 0, 32]]
+    # the big job has waited past starve_s: it takes the whole budget (128 rows); the small one
+    # waits for the next step (only the first job may go past the budget)
+    assert res["starve_step1"] == [[1, 0, 128]]
     # neither has waited that long: least remaining work first, as before
     assert res["starve_none"] == [[2, 0, 70], [1, 0, 32]]
 
