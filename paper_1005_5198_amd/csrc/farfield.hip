@@ -270,10 +270,17 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
 
     unsigned long long n_in = 0, n_out = 0;
     const int64_t W = a.i1 - a.i0;
+    // the coefficients stay in registers for every ray of this thread
+    double T1[FAR_P], T2[FAR_P];
+#pragma unroll
+    for (int n = 0; n < FAR_P; ++n) {
+        T1[n] = sm.tc[n];
+        T2[n] = sm.tc[FAR_P + n];
+    }
     // A wave takes 8 x 8-ray blocks of the patch (block wave + 4 r, r < 8), so the
     // rays of one wave land on few pixels and the binning atomics aggregate well.
     const int wave = tid >> 6;
-#pragma unroll 1
+#pragma unroll 2
     for (int r = 0; r < FAR_ROWS; ++r) {
         const int b = wave + (FAR_THREADS / 64) * r;
         const int64_t i = ib + 8 * (b % (PATCH_X / 8)) + (lane & 7);
@@ -282,11 +289,11 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
         const double x1 = ray_coord(a.sx0, i, a.spx);
         const double x2 = ray_coord(a.sy0, j, a.spy);
         const double nw1 = ox - x1, nw2 = oy - x2;   // -w
-        double S1 = sm.tc[FAR_P - 1], S2 = sm.tc[2 * FAR_P - 1];
+        double S1 = T1[FAR_P - 1], S2 = T2[FAR_P - 1];
 #pragma unroll
         for (int n = FAR_P - 2; n >= 0; --n) {
-            const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, sm.tc[n]));
-            const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, sm.tc[FAR_P + n]));
+            const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, T1[n]));
+            const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, T2[n]));
             S1 = q1;
             S2 = q2;
         }

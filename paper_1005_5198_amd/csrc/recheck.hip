@@ -164,6 +164,7 @@ __device__ __forceinline__ void wave_sync() {
 // Stage A for the entries held one per lane (valid lanes only): lanes are
 // grouped by map, and each group runs with its map's parameters in scalar
 // registers. Rays are decided, or marked for the exact stage.
+template <bool ALL_UNIT>
 __device__ inline void batch_stage_a(const BatchArgs &b, QueueEntry e, bool valid) {
     uint64_t pending = __ballot(valid);
     while (pending) {
@@ -180,7 +181,8 @@ __device__ inline void batch_stage_a(const BatchArgs &b, QueueEntry e, bool vali
             const int64_t W = a.i1 - a.i0;
             const int64_t i = a.i0 + (int64_t)(e.ray % (uint64_t)W);
             const int64_t j = a.j0 + (int64_t)(e.ray / (uint64_t)W);
-            ok = a.lens_m == nullptr ? fast_ray<true>(a, i, j, code) : fast_ray<false>(a, i, j, code);
+            if (ALL_UNIT || a.lens_m == nullptr) ok = fast_ray<true>(a, i, j, code);
+            else ok = fast_ray<false>(a, i, j, code);
             if (ok) {
                 if (code >= 0) atomicAdd(a.map + code, 1u);
             } else {
@@ -200,6 +202,29 @@ __device__ inline void batch_stage_a(const BatchArgs &b, QueueEntry e, bool vali
 }
 
 // Exact stage for up to 64 entries held one per lane: one wave per ray.
+// Stage A of one queued ray (wave-uniform entry) by the whole wave: lanes split the
+// lenses. Used for a wave's last few rays, where one ray per lane would leave the
+// GPU mostly idle while each lane walks every lens.
+__device__ inline void batch_stage_a_wave(const BatchArgs &b, QueueEntry e) {
+    const BatchMap &m = b.maps[e.map];
+    const RecheckArgs a = make_uniform(batch_recheck_args(m));
+    const int64_t W = a.i1 - a.i0;
+    const int64_t i = a.i0 + (int64_t)(e.ray % (uint64_t)W);
+    const int64_t j = a.j0 + (int64_t)(e.ray / (uint64_t)W);
+    int code = CODE_OUT;
+    const bool ok = a.lens_m == nullptr ? fast_ray_wave<true>(a, i, j, code) : fast_ray_wave<false>(a, i, j, code);
+    if (__lane_id() == 0) {
+        if (ok) {
+            if (code >= 0) atomicAdd(a.map + code, 1u);
+            atomicAdd(a.counters + (code >= 0 ? C_IN : C_OUT), 1ull);
+        } else {
+            uint32_t *const unres = m.unres_bits;
+            atomicOr(unres + (e.ray >> 5), 1u << (e.ray & 31u));
+            atomicOr(b.unresolved, 1u);
+        }
+    }
+}
+
 __device__ inline void batch_stage_b(const BatchArgs &b, QueueEntry e, int n_valid) {
     const int lane = __lane_id();
     for (int s = 0; s < n_valid; ++s) {
@@ -216,12 +241,13 @@ __device__ inline void batch_stage_b(const BatchArgs &b, QueueEntry e, int n_val
 }
 
 // Persistent scan of the batch's bitmaps (STAGE 0: flag bits -> stage A;
-// STAGE 1: unresolved bits -> exact stage). Wave k takes the 64-word blocks
-// k, k + n_waves, k + 2 n_waves, ... of the batch's word space (interleaved, so
-// every wave sees a mix of all maps and no atomics are needed), compacts their
-// set bits into its own ring buffer in LDS, and evaluates them 64 at a time,
-// one per lane. A wave leaves when its blocks are done and its buffer is empty.
-template <int STAGE>
+// STAGE 1: unresolved bits -> exact stage). The batch's words are dealt to the
+// waves one at a time (lane l of wave k reads word k + (t + l) n_waves), so a
+// dense run of flagged rays - a crowded lens region fills whole rows of them -
+// is spread over many waves instead of queueing in one. Each wave compacts its
+// set bits into its own ring buffer in LDS and evaluates them 64 at a time, one
+// per lane. A wave leaves when its words are done and its buffer is empty.
+template <int STAGE, bool ALL_UNIT>
 __global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs b) {
     if (STAGE == 1 && *b.unresolved == 0u) return;
     constexpr int RING = 128;
@@ -232,16 +258,22 @@ __global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs
     int head = 0, tail = 0;  // wave-uniform; tail - head < 64 between evaluations
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t fetch = wave_id * BITMAP_WORD_ALIGN; fetch < b.total_words; fetch += n_waves * BITMAP_WORD_ALIGN) {
-        int lo = 0, hi = b.n_maps - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (b.maps[mid].word_begin <= fetch) lo = mid;
-            else hi = mid - 1;
+    for (int64_t t0 = 0; wave_id + t0 * n_waves < b.total_words; t0 += 64) {
+        const int64_t word = wave_id + (t0 + lane) * n_waves;
+        uint32_t bits = 0u;
+        int lo = 0;
+        int64_t w = 0;
+        if (word < b.total_words) {
+            int hi = b.n_maps - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (b.maps[mid].word_begin <= word) lo = mid;
+                else hi = mid - 1;
+            }
+            const BatchMap &m = b.maps[lo];
+            w = word - m.word_begin;
+            bits = (STAGE == 0 ? m.flag_bits : m.unres_bits)[w];
         }
-        const BatchMap &m = b.maps[lo];
-        const int64_t w = fetch - m.word_begin + lane;
-        uint32_t bits = (STAGE == 0 ? m.flag_bits : m.unres_bits)[w];
         for (;;) {
             const uint64_t hm = __ballot(bits != 0u);
             if (!hm) break;
@@ -257,7 +289,7 @@ __global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs
                 const QueueEntry e = ring[(head + lane) % RING];
                 head += 64;
                 wave_sync();
-                if (STAGE == 0) batch_stage_a(b, e, true);
+                if (STAGE == 0) batch_stage_a<ALL_UNIT>(b, e, true);
                 else batch_stage_b(b, e, 64);
             }
         }
@@ -267,7 +299,13 @@ __global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs
         QueueEntry e{0u, 0u};
         if (lane < left) e = ring[(head + lane) % RING];
         if (STAGE == 0) {
-            batch_stage_a(b, e, lane < left);
+            // the last few rays: one wave per ray (lenses split over the lanes)
+            for (int s = 0; s < left; ++s) {
+                QueueEntry es;
+                es.map = (uint32_t)__builtin_amdgcn_readlane((int)e.map, s);
+                es.ray = (uint32_t)__builtin_amdgcn_readlane((int)e.ray, s);
+                batch_stage_a_wave(b, es);
+            }
         } else {
             batch_stage_b(b, e, left);
         }
@@ -300,8 +338,10 @@ hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_onl
 hipError_t launch_recheck_batch(const BatchArgs &b, hipStream_t stream) {
     if (b.total_words <= 0) return hipSuccess;
     const dim3 grid(2048), block(256);
-    hipLaunchKernelGGL(recheck_scan_batch_kernel<0>, grid, block, 0, stream, b);
-    hipLaunchKernelGGL(recheck_scan_batch_kernel<1>, grid, block, 0, stream, b);
+    // stage A in a kernel of its own for batches of unit-mass maps only (fewer registers)
+    if (b.unit_masses) hipLaunchKernelGGL((recheck_scan_batch_kernel<0, true>), grid, block, 0, stream, b);
+    else hipLaunchKernelGGL((recheck_scan_batch_kernel<0, false>), grid, block, 0, stream, b);
+    hipLaunchKernelGGL((recheck_scan_batch_kernel<1, false>), grid, block, 0, stream, b);
     return hipGetLastError();
 }
 

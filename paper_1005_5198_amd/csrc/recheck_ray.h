@@ -42,6 +42,20 @@ __device__ __forceinline__ T make_uniform(const T &v) {
 constexpr int CODE_OUT = -1;
 constexpr int CODE_SINGULAR = -2;
 
+// Lens reads through a global-address-space pointer. A batch's descriptors hold
+// plain (generic) pointers; read through those, the lens loop compiles to flat
+// loads that wait on every memory counter each iteration.
+typedef __attribute__((address_space(1))) const double global_double;
+__device__ __forceinline__ double lens_x(const RecheckArgs &a, int64_t k) {
+    return ((global_double *)a.lens_xy)[2 * k];
+}
+__device__ __forceinline__ double lens_y(const RecheckArgs &a, int64_t k) {
+    return ((global_double *)a.lens_xy)[2 * k + 1];
+}
+__device__ __forceinline__ double lens_mass(const RecheckArgs &a, int64_t k) {
+    return ((global_double *)a.lens_m)[k];
+}
+
 // Image-plane position of ray (i, j): the regular grid's cell centre, or the
 // ray's Philox-random point of the shooting rectangle.
 __device__ __forceinline__ void ray_xy(const RecheckArgs &a, int64_t i, int64_t j, double &x1, double &x2) {
@@ -59,11 +73,11 @@ __device__ inline int exact_ray_thread(const RecheckArgs &a, int64_t i, int64_t 
     ray_xy(a, i, j, x1, x2);
     double a1 = 0.0, a2 = 0.0;
     for (int64_t k = 0; k < a.n_lens; ++k) {
-        const double d1 = x1 - a.lens_xy[2 * k];
-        const double d2 = x2 - a.lens_xy[2 * k + 1];
+        const double d1 = x1 - lens_x(a, k);
+        const double d2 = x2 - lens_y(a, k);
         const double r2 = d1 * d1 + d2 * d2;
         if (r2 == 0.0) return CODE_SINGULAR;
-        const double m = UNIT ? 1.0 : a.lens_m[k];
+        const double m = UNIT ? 1.0 : lens_mass(a, k);
         const double f = m / r2;
         a1 += f * d1;
         a2 += f * d2;
@@ -101,11 +115,11 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
         double t1 = 0.0, t2 = 0.0;
         bool zero = false;
         if (k < a.n_lens) {
-            const double d1 = x1 - a.lens_xy[2 * k];
-            const double d2 = x2 - a.lens_xy[2 * k + 1];
+            const double d1 = x1 - lens_x(a, k);
+            const double d2 = x2 - lens_y(a, k);
             const double r2 = d1 * d1 + d2 * d2;
             zero = (r2 == 0.0);
-            const double m = UNIT ? 1.0 : a.lens_m[k];
+            const double m = UNIT ? 1.0 : lens_mass(a, k);
             const double f = m / r2;
             t1 = f * d1;
             t2 = f * d2;
@@ -145,8 +159,8 @@ __device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int 
     bool tiny = false;
 #pragma unroll 4
     for (int64_t k = 0; k < a.n_lens; ++k) {
-        const double d1 = x1 - a.lens_xy[2 * k];
-        const double d2 = x2 - a.lens_xy[2 * k + 1];
+        const double d1 = x1 - lens_x(a, k);
+        const double d2 = x2 - lens_y(a, k);
         const double r2 = __builtin_fma(d1, d1, d2 * d2);
         tiny |= !(r2 > 1e-200);
         double rc = __builtin_amdgcn_rcp(r2);
@@ -154,7 +168,7 @@ __device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int 
         rc = __builtin_fma(rc, e, rc);
         e = __builtin_fma(-r2, rc, 1.0);
         rc = __builtin_fma(rc, e, rc);
-        if (!UNIT) rc = rc * a.lens_m[k];
+        if (!UNIT) rc = rc * lens_mass(a, k);
         a1 = __builtin_fma(d1, rc, a1);
         a2 = __builtin_fma(d2, rc, a2);
         S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
@@ -197,8 +211,8 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
     double a1 = 0.0, a2 = 0.0, S = 0.0;
     int tiny = 0;
     for (int64_t k = __lane_id(); k < a.n_lens; k += 64) {
-        const double d1 = x1 - a.lens_xy[2 * k];
-        const double d2 = x2 - a.lens_xy[2 * k + 1];
+        const double d1 = x1 - lens_x(a, k);
+        const double d2 = x2 - lens_y(a, k);
         const double r2 = __builtin_fma(d1, d1, d2 * d2);
         tiny |= !(r2 > 1e-200);
         double rc = __builtin_amdgcn_rcp(r2);
@@ -206,7 +220,7 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
         rc = __builtin_fma(rc, e, rc);
         e = __builtin_fma(-r2, rc, 1.0);
         rc = __builtin_fma(rc, e, rc);
-        if (!UNIT) rc = rc * a.lens_m[k];
+        if (!UNIT) rc = rc * lens_mass(a, k);
         a1 = __builtin_fma(d1, rc, a1);
         a2 = __builtin_fma(d2, rc, a2);
         S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);

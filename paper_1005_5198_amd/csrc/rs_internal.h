@@ -86,9 +86,9 @@ constexpr int FF_NEAR_CAP = 4096;
 constexpr int FF_REC_DOUBLES = 36;
 
 // Random rays: expected rays per bin (a block's capacity is 2048, so a bin
-// overflows it only beyond seven standard deviations, and then takes a second
-// pass), and the largest launch.
-constexpr int64_t RAND_BIN_RAYS = 1740;
+// overflows it only beyond three standard deviations, about one bin in 3000,
+// and then takes a second pass), and the largest launch.
+constexpr int64_t RAND_BIN_RAYS = 1900;
 constexpr int64_t RAND_CHUNK_RAYS = int64_t(1) << 26;
 
 struct RecheckArgs {

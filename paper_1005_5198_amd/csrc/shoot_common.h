@@ -101,9 +101,10 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
             float fx = 1.0e18f, fy = 0.0f, fm = 0.0f;  // padding lens: far away, massless
             if (s < cnt) {
                 const int64_t k = t0 + s;
-                const double X = a.lens_xy[2 * k];
-                const double Y = a.lens_xy[2 * k + 1];
-                const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
+                // global-address-space reads (a batch descriptor's pointers are generic)
+                const double X = ((global_double *)a.lens_xy)[2 * k];
+                const double Y = ((global_double *)a.lens_xy)[2 * k + 1];
+                const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
                 const double Lx = X - ox, Ly = Y - oy;
                 fx = (float)Lx;
                 fy = (float)Ly;
