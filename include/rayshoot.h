@@ -266,7 +266,8 @@ typedef struct {
     size_t hbm_budget_bytes;  /* device pool for admitted requests (allocated once, by the server) */
     int32_t max_inflight;     /* requests admitted at once (slots), >= 1 */
     int32_t mode;             /* RS_FP32 or RS_MIXED, for every request */
-    double slice_ms;          /* target GPU time of one launch step; <= 0 selects 10 ms */
+    double slice_ms;          /* target GPU time of one launch step; <= 0 selects 10 ms; four
+                                 times that while requests wait for admission */
     double starve_s;          /* a request older than this is served first; <= 0 selects 0.5 s */
 } rs_server_cfg;
 

@@ -141,7 +141,10 @@ void rs_server::finish(Request &r, int state, int error) {
 
 // Plan and enqueue one step (called with the lock held). Returns false if there was nothing to run.
 bool rs_server::launch_step() {
-    const double target = rate * (cfg.slice_ms > 0 ? cfg.slice_ms : 10.0) * 1e-3;
+    // Requests waiting for admission mean the GPU is the bottleneck: longer steps then
+    // trade a little responsiveness for less per-step overhead.
+    const double slice_s = (cfg.slice_ms > 0 ? cfg.slice_ms : 10.0) * 1e-3 * (policy.waiting() > 0 ? 4.0 : 1.0);
+    const double target = rate * slice_s;
     std::vector<Slice> slices = policy.plan(target, now_s(), 0.25, cfg.starve_s > 0 ? cfg.starve_s : 0.5);
     if (slices.empty()) return false;
     std::vector<rs_map_request> batch;
