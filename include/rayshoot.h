@@ -31,10 +31,14 @@
  *             rigorous bound on its source-position error, and rays whose
  *             bound reaches a pixel edge are re-evaluated in FP64 with the
  *             plain definition (lens order, no fused multiply-add, IEEE
- *             division). A first FP64 stage with fused multiply-adds and a
- *             rigorous bound decides almost every queued ray; only rays it
- *             cannot place run the exact sequence. The count map equals the
- *             FP64 definition's map.
+ *             division). On the regular grid a first stage evaluates each
+ *             queued ray from its super-patch's FP64 far-field expansion (the
+ *             RS_FARFIELD one, below) plus the lenses listed next to the
+ *             super-patch, under that mode's rigorous bound; the rays it
+ *             cannot place (and every queued random ray) go to an FP64 stage
+ *             over every lens with fused multiply-adds and a rigorous bound,
+ *             and only the rays that stage cannot place run the exact sequence.
+ *             The count map equals the FP64 definition's map.
  *   RS_FP32   the same FP32 sum, binned directly (no bound, no re-check).
  *   RS_FARFIELD  the tree codes' idea (Section 2, Eq. (hierarchical): distant
  *             lenses grouped, with higher multipoles) taken to all orders: per
@@ -111,6 +115,8 @@ typedef struct {
     uint64_t rays_out;        /* rays outside the map or with a non-finite position */
     uint64_t rays_singular;   /* rays exactly on a lens */
     uint64_t rays_rechecked;  /* RS_MIXED: rays re-evaluated in FP64 */
+    uint64_t rays_rechecked_direct; /* of those, rays re-evaluated against every lens (the far-field
+                                       first stage could not place them, or did not apply) */
 } rs_map_stats;
 
 /* Library version string. */

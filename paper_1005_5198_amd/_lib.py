@@ -50,7 +50,7 @@ class MapParams(ctypes.Structure):
 class MapStats(ctypes.Structure):
     _fields_ = [("rays_shot", ctypes.c_uint64), ("rays_in_map", ctypes.c_uint64),
                 ("rays_out", ctypes.c_uint64), ("rays_singular", ctypes.c_uint64),
-                ("rays_rechecked", ctypes.c_uint64)]
+                ("rays_rechecked", ctypes.c_uint64), ("rays_rechecked_direct", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -150,6 +150,7 @@ int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_ho
         stats_host[k].rays_out = q[C_OUT];
         stats_host[k].rays_singular = q[C_SING];
         stats_host[k].rays_rechecked = q[C_RECHECK];
+        stats_host[k].rays_rechecked_direct = q[C_RECHECK];   // a batch has no far-field stage
         stats_host[k].rays_shot = q[C_IN] + q[C_OUT] + q[C_SING];
     }
     return RS_OK;

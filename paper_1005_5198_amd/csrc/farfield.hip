@@ -138,9 +138,12 @@ struct FarSuperSmem {
 // Level 1: one block per super-patch. Far lenses -> coefficients C about zS;
 // the others -> the super-patch's lens list (a count above FF_NEAR_CAP means
 // the list is incomplete and the patches scan every lens instead).
-template <bool UNIT>
+// RECHECK: the mixed mode's re-check stage needs the records only when the
+// deflection launch queued rays.
+template <bool UNIT, bool RECHECK>
 __global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const ShootArgs a) {
     __shared__ FarSuperSmem sm;
+    if (RECHECK && *a.qcount == 0) return;
     const int64_t sp = blockIdx.x;
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
@@ -166,6 +169,38 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const Shoot
     double *rec = a.ff_super + sp * (int64_t)FAR_REC;
     if (threadIdx.x < FAR_REC) rec[threadIdx.x] = sm.out[threadIdx.x];
     if (threadIdx.x == 0) list[0] = sm.count;
+}
+
+// Pixel decision of one ray from its FP64 deflection (a1, a2) = expansion +
+// directly summed lenses. Bound terms in source units: far_err (truncation and
+// rounding of the expansion), SFAR (sum of |m|/|d| over the expanded lenses,
+// which bounds the far sum by 1.34 SFAR), SDEF (the definition's rounding
+// weight of those lenses), snear and n_near (the direct sum, with its additions
+// onto the far sum), plus the definition's own lens-order rounding and the
+// epilogue. Returns the pixel, OUT, or FLAGGED.
+__device__ __forceinline__ int far_decide(const ShootArgs &a, double x1, double x2, double a1, double a2,
+                                          double far_err, double SFAR, double SDEF, double snear, int n_near,
+                                          bool sane_in) {
+    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
+    const double y1 = a.c1 * x1 - a1;
+    const double y2 = a.c2 * x2 - a2;
+    const double u = (y1 - a.tx0) * a.inv_pixw;
+    const double v = (y2 - a.ty0) * a.inv_pixh;
+    const double near_err = ((double)n_near + 10.0) * U64 * 1.001 * snear + (double)n_near * U64 * 1.34 * SFAR;
+    const double def_sum = kN * (snear + SDEF);
+    const double eu = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c1 * x1) + fabs(a1) + fabs(a.tx0));
+    const double ev = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c2 * x2) + fabs(a2) + fabs(a.ty0));
+    const double Mu = 1.001 * eu * a.inv_pixw, Mv = 1.001 * ev * a.inv_pixh;
+    const double fu = floor(u), fv = floor(v);
+    const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
+    const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
+    const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
+    const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
+    const bool sane = sane_in && isfinite(Mu) && isfinite(Mv) && isfinite(u) && isfinite(v);
+    if (sane && ok_u && ok_v) return (int)((int64_t)fv * a.npx + (int64_t)fu);
+    if (sane && (out_u || out_v)) return OUT;
+    return FLAGGED;
 }
 
 struct FarSmem {
@@ -265,7 +300,6 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
     // the translation and the evaluation (per-level factors, generous constants).
     const double far_err = TRUNC_S + TRUNC_P + (NFAR_S + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_S +
                            (NFAR_P + 16.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_P;
-    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
     const double SDEF = SDEF_S + SDEF_P;
 
     unsigned long long n_in = 0, n_out = 0;
@@ -309,28 +343,7 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
             a2 = __builtin_fma(f, e2, a2);
             snear = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), snear);
         }
-        const double y1 = a.c1 * x1 - a1;
-        const double y2 = a.c2 * x2 - a2;
-        const double u = (y1 - a.tx0) * a.inv_pixw;
-        const double v = (y2 - a.ty0) * a.inv_pixh;
-        // Error bound in source units: ours (far field, near sum and its additions onto
-        // the far sum, epilogue) and the definition's own lens-order rounding.
-        const double near_err =
-            ((double)n_near + 10.0) * U64 * 1.001 * snear + (double)n_near * U64 * 1.34 * SFAR;
-        const double def_sum = kN * (snear + SDEF);
-        const double eu = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c1 * x1) + fabs(a1) + fabs(a.tx0));
-        const double ev = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c2 * x2) + fabs(a2) + fabs(a.ty0));
-        const double Mu = 1.001 * eu * a.inv_pixw, Mv = 1.001 * ev * a.inv_pixh;
-        const double fu = floor(u), fv = floor(v);
-        const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
-        const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
-        const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
-        const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
-        const bool sane = !tiny && !all_flagged && isfinite(Mu) && isfinite(Mv) && isfinite(u) && isfinite(v);
-        int code;
-        if (sane && ok_u && ok_v) code = (int)((int64_t)fv * a.npx + (int64_t)fu);
-        else if (sane && (out_u || out_v)) code = OUT;
-        else code = FLAGGED;
+        int code = far_decide(a, x1, x2, a1, a2, far_err, SFAR, SDEF, snear, n_near, !tiny && !all_flagged);
         if (!valid) code = INT32_MIN;
 
         n_in += __builtin_popcountll(__ballot(code >= 0));
@@ -349,7 +362,110 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
     }
 }
 
+// Re-check stage of the mixed mode on the regular grid, one thread per queued
+// ray: the ray's super-patch expansion (Horner in -w = zS - z, the same series
+// the patch kernel re-centres) plus the super-patch's listed lenses summed
+// directly in FP64, under the patch kernel's bound with no patch level. A ray
+// it places is binned and its entry marked RESOLVED; the others (a list over
+// FF_NEAR_CAP included) are counted in *qlive and left for the FP64 stage over
+// every lens. Queue entries of one deflection wave are adjacent and share a
+// super-patch, so a wave walks one list.
+template <bool UNIT>
+__global__ __launch_bounds__(256) void recheck_far_kernel(const ShootArgs a, uint32_t *qlive) {
+    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+    const uint32_t n = *a.qcount;
+    const int64_t W = a.i1 - a.i0;
+    unsigned long long n_in = 0, n_out = 0;
+    uint32_t left = 0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        const uint32_t q = a.queue[idx];
+        const int64_t ri = (int64_t)(q % (uint64_t)W), rj = (int64_t)(q / (uint64_t)W);
+        const int64_t i = a.i0 + ri, j = a.jc0 + rj;
+        const int64_t sp = (rj / (PATCH_Y * FF_SP_Y)) * a.ff_sbx + ri / (PATCH_X * FF_SP_X);
+        const int32_t *list = a.ff_near + sp * (int64_t)(1 + FF_NEAR_CAP);
+        const int32_t listed = list[0];
+        int code = FLAGGED;
+        if (listed <= FF_NEAR_CAP) {
+            const double *rec = a.ff_super + sp * (int64_t)FAR_REC;
+            double cx, cy, H;
+            super_geometry(a, sp, cx, cy, H);
+            const double x1 = ray_coord(a.sx0, i, a.spx);
+            const double x2 = ray_coord(a.sy0, j, a.spy);
+            const double nw1 = cx - x1, nw2 = cy - x2;   // -w
+            double S1 = rec[FAR_P - 1], S2 = rec[2 * FAR_P - 1];
+#pragma unroll
+            for (int nn = FAR_P - 2; nn >= 0; --nn) {
+                const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, rec[nn]));
+                const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, rec[FAR_P + nn]));
+                S1 = q1;
+                S2 = q2;
+            }
+            double a1 = S1, a2 = -S2;
+            double snear = 0.0;
+            bool tiny = false;
+            for (int l = 0; l < listed; ++l) {
+                const int64_t k = list[1 + l];
+                const double e1 = x1 - ((global_double *)a.lens_xy)[2 * k];
+                const double e2 = x2 - ((global_double *)a.lens_xy)[2 * k + 1];
+                const double r2 = __builtin_fma(e1, e1, e2 * e2);
+                tiny |= !(r2 > 1e-200);
+                const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
+                const double f = m * rcp64(r2);
+                a1 = __builtin_fma(f, e1, a1);
+                a2 = __builtin_fma(f, e2, a2);
+                snear = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), snear);
+            }
+            const double SFAR = rec[2 * FAR_P], TRUNC = rec[2 * FAR_P + 1], SDEF = rec[2 * FAR_P + 2];
+            const double NFAR = rec[2 * FAR_P + 3];
+            const double far_err = TRUNC + (NFAR + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR;
+            code = far_decide(a, x1, x2, a1, a2, far_err, SFAR, SDEF, snear, listed, !tiny);
+        }
+        if (code == FLAGGED) {
+            ++left;
+        } else {
+            a.queue[idx] = q | RESOLVED;
+            if (code >= 0) {
+                ++n_in;
+                if (a.pix_out) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+                else atomicAdd(a.map + code, 1u);
+            } else {
+                ++n_out;
+                if (a.pix_out) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        n_in += __shfl_xor(n_in, off);
+        n_out += __shfl_xor(n_out, off);
+        left += __shfl_xor(left, off);
+    }
+    if (__lane_id() == 0) {
+        if (n_in) atomicAdd(a.counters + C_IN, n_in);
+        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
+        if (left) atomicAdd(qlive, left);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_rays, hipStream_t stream) {
+    const int64_t rows = a.jc1 - a.jc0;
+    const int64_t nby = (rows + PATCH_Y - 1) / PATCH_Y;
+    const int64_t n_super = a.ff_sbx * ((nby + FF_SP_Y - 1) / FF_SP_Y);
+    if (n_super <= 0 || max_rays <= 0) return hipSuccess;
+    const bool unit = a.lens_m == nullptr;
+    if (unit) hipLaunchKernelGGL((farfield_super_kernel<true, true>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
+    else hipLaunchKernelGGL((farfield_super_kernel<false, true>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t blocks = (max_rays + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (unit) hipLaunchKernelGGL((recheck_far_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, stream, a, qlive);
+    else hipLaunchKernelGGL((recheck_far_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, stream, a, qlive);
+    return hipGetLastError();
+}
 
 hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     const int64_t rows = a.jc1 - a.jc0;
@@ -360,8 +476,8 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     const bool unit = a.lens_m == nullptr;
     const bool pix = a.pix_out != nullptr;
     const dim3 block(FAR_THREADS);
-    if (unit) hipLaunchKernelGGL((farfield_super_kernel<true>), dim3((unsigned)n_super), block, 0, stream, a);
-    else hipLaunchKernelGGL((farfield_super_kernel<false>), dim3((unsigned)n_super), block, 0, stream, a);
+    if (unit) hipLaunchKernelGGL((farfield_super_kernel<true, false>), dim3((unsigned)n_super), block, 0, stream, a);
+    else hipLaunchKernelGGL((farfield_super_kernel<false, false>), dim3((unsigned)n_super), block, 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)patches);

@@ -10,7 +10,10 @@
 // RS_EXACT_RECHECK runs the exact sequence for every queued ray instead (one
 // thread per ray).
 //
-// Single map: the queue holds uint32 chunk-relative ray indices.
+// Single map: the queue holds uint32 chunk-relative ray indices. On the
+// regular grid the far-field stage (farfield.hip) runs first and marks the
+// entries it decided RESOLVED; stage A skips them and picks its form from the
+// number left (*qlive).
 // Batch: the deflection kernel sets one bit per flagged ray in each map's
 // bitmap; a persistent scan compacts the set bits per wave and the map's
 // descriptor supplies its parameters.
@@ -68,19 +71,27 @@ __global__ __launch_bounds__(256) void recheck_exact_kernel(const RecheckArgs a)
         place(a, i, j, code);
     }
     count_wave(a.counters, n_in, n_out, n_sing);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
+        atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
+        atomicAdd(a.counters + C_DIRECT, (unsigned long long)n);
+    }
 }
 
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) {
     const uint32_t n = *a.qcount;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
-    if (n < WAVE_STAGE_MAX) return;   // recheck_fast_wave_kernel takes short queues
+    const uint32_t live = a.qlive ? *a.qlive : n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (n) atomicAdd(a.counters + C_RECHECK, (unsigned long long)n);
+        if (live) atomicAdd(a.counters + C_DIRECT, (unsigned long long)live);
+    }
+    if (live < WAVE_STAGE_MAX) return;   // recheck_fast_wave_kernel takes short queues
     const int64_t W = a.i1 - a.i0;
     unsigned long long n_in = 0, n_out = 0, n_sing = 0;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
         const uint32_t q = a.queue[idx];
+        if (q & RESOLVED) continue;
         const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
         const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
         int code;
@@ -94,28 +105,39 @@ __global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) 
     count_wave(a.counters, n_in, n_out, n_sing);
 }
 
-// Stage A for a short queue: one wave per queued ray, rays dealt to the waves in turn.
+// Stage A for few live entries: one wave per ray. Entries are dealt to the
+// waves 64 at a time (lane l of wave k reads entry k + (t + l) n_waves), so a
+// long queue whose entries the far-field stage mostly decided costs each wave
+// a few vector loads, and neighbouring live rays go to different waves.
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_fast_wave_kernel(const RecheckArgs a) {
     const uint32_t n = *a.qcount;
-    if (n >= WAVE_STAGE_MAX) return;
+    const uint32_t live = a.qlive ? *a.qlive : n;
+    if (live >= WAVE_STAGE_MAX || live == 0) return;
     const int64_t W = a.i1 - a.i0;
     const int lane = __lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     unsigned long long n_in = 0, n_out = 0, n_sing = 0;
-    for (uint32_t idx = wave_id; idx < n; idx += n_waves) {
-        const uint32_t q = a.queue[idx];
-        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
-        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
-        int code = 0;
-        const bool decided = fast_ray_wave<UNIT>(a, i, j, code);
-        if (lane == 0) {
-            if (decided) {
-                tally(code, n_in, n_out, n_sing);
-                place(a, i, j, code);
-            } else {
-                a.queue[idx] = q | UNRESOLVED;
+    for (uint64_t t0 = 0; (uint64_t)wave_id + t0 * n_waves < n; t0 += 64) {
+        const uint64_t idx64 = (uint64_t)wave_id + (t0 + (uint64_t)lane) * n_waves;
+        const uint32_t q_lane = idx64 < n ? a.queue[idx64] : RESOLVED;
+        uint64_t todo = __ballot(!(q_lane & RESOLVED));
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)q_lane, src);
+            const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
+            const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
+            int code = 0;
+            const bool decided = fast_ray_wave<UNIT>(a, i, j, code);
+            if (lane == src) {
+                if (decided) {
+                    tally(code, n_in, n_out, n_sing);
+                    place(a, i, j, code);
+                } else {
+                    a.queue[idx64] = q | UNRESOLVED;
+                }
             }
         }
     }

@@ -26,6 +26,7 @@
 namespace rs {
 
 constexpr uint32_t UNRESOLVED = 0x80000000u;  // queue mark: stage A could not place the ray
+constexpr uint32_t RESOLVED = 0x40000000u;    // queue mark: the far-field stage placed the ray
 
 // A copy of a wave-uniform struct whose every 32-bit word goes through
 // readfirstlane, so the compiler keeps it in scalar registers.

@@ -30,10 +30,10 @@ constexpr int NEAR_MAX = 64;                  // per-block list of lenses close 
 
 // Workspace layout (bytes).
 constexpr size_t WS_COUNTERS = 0;             // uint64 [8]: in, out, singular, rechecked, spare
-constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] queue lengths
+constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] queue lengths, then [n_chunks] live counts
 constexpr int64_t CHUNK_RAYS = int64_t(1) << 27;  // rays per launch (queue capacity)
 
-enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3 };
+enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3, C_DIRECT = 4 };
 constexpr int N_COUNTERS = 8;
 
 struct ShootArgs {
@@ -106,6 +106,7 @@ struct RecheckArgs {
     unsigned long long *counters;
     uint32_t *queue;       // stage A marks unresolved entries in place
     const uint32_t *qcount;
+    const uint32_t *qlive; // entries the far-field stage left undecided, or nullptr (no such stage)
     int32_t random;        // Philox-random ray positions (RS_RANDOM_RAYS)
     uint64_t seed;
 };
@@ -246,6 +247,10 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream);
 // Random rays: count into bins, scan, scatter, then deflect bin by bin.
 hipError_t launch_shoot_random(const ShootArgs &a, int mode, hipStream_t stream);
 hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);
+// Mixed mode on the regular grid: the super-patch expansions of the launch, then
+// the far-field re-check stage over the queue (a.queue, a.qcount); it counts the
+// entries it leaves undecided in *qlive.
+hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_rays, hipStream_t stream);
 
 hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream);
 hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream);

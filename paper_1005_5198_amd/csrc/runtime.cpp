@@ -34,7 +34,8 @@ struct Plan {
     int64_t W = 0, H = 0;
     int64_t rows_per_chunk = 0, n_chunks = 0;
     int64_t queue_cap = 0;   // uint32 entries (mixed only)
-    size_t qcount_bytes = 0; // WS_QCOUNT + 4 * n_chunks, 256-aligned
+    size_t qcount_bytes = 0; // WS_QCOUNT + 8 * n_chunks (queue lengths, live counts), 256-aligned
+    bool far_recheck = false; // mixed mode on the regular grid: far-field re-check stage first
     // Random rays: bin arrays for the largest number of bins of a launch, and
     // the sorted ray list (index, x, y) of the largest launch.
     bool random = false;
@@ -103,9 +104,10 @@ Plan make_plan(const rs_map_params *p) {
     pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
     const int64_t rows_cap = pl.H < rows ? pl.H : rows;
     pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
-    pl.qcount_bytes = (WS_QCOUNT + 4 * (size_t)pl.n_chunks + 255) / 256 * 256;
+    pl.qcount_bytes = (WS_QCOUNT + 8 * (size_t)pl.n_chunks + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
-    if (p->mode == RS_FARFIELD && pl.n_chunks > 0) {
+    pl.far_recheck = p->mode == RS_MIXED && !pl.random && !(p->flags & RS_EXACT_RECHECK);
+    if ((p->mode == RS_FARFIELD || pl.far_recheck) && pl.n_chunks > 0) {
         const int64_t nbx = (pl.W + PATCH_X - 1) / PATCH_X;
         const int64_t nby = (rows_cap + PATCH_Y - 1) / PATCH_Y;
         pl.super_cap = ((nbx + FF_SP_X - 1) / FF_SP_X) * ((nby + FF_SP_Y - 1) / FF_SP_Y);
@@ -198,7 +200,8 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         return fail(RS_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, pl.bytes);
 
     const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
-    hipError_t e = launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, pl.n_chunks, stream);
+    hipError_t e =
+        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 2 * pl.n_chunks, stream);
     if (e != hipSuccess) return hip_fail(e, "fill kernel");
 
     char *ws = static_cast<char *>(workspace);
@@ -269,6 +272,11 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         a.ray_y = reinterpret_cast<double *>(ws + pl.y_off);
     }
 
+    if (p->mode == RS_FARFIELD || pl.far_recheck) {
+        a.ff_sbx = (a.nbx + FF_SP_X - 1) / FF_SP_X;
+        a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
+        a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
+    }
     if (shape < 0 && !pl.random && p->mode != RS_FARFIELD) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
     hipEvent_t t_first = nullptr, t_last = nullptr;
     if (kernel_ms) {
@@ -292,9 +300,6 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
             a.inv_bh = (double)a.nby_r / p->sh;
             e = launch_shoot_random(a, p->mode, stream);
         } else if (p->mode == RS_FARFIELD) {
-            a.ff_sbx = (a.nbx + FF_SP_X - 1) / FF_SP_X;
-            a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
-            a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
             e = launch_farfield(a, stream);
         } else {
             e = launch_shoot(a, p->mode, shape, stream);
@@ -312,6 +317,13 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         if (p->mode != RS_FP32) {
             r.jc0 = a.jc0;
             r.qcount = a.qcount;
+            r.qlive = nullptr;
+            if (pl.far_recheck) {
+                uint32_t *qlive = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + pl.n_chunks + c;
+                e = launch_recheck_far(a, qlive, (a.jc1 - a.jc0) * pl.W, stream);
+                if (e != hipSuccess) return hip_fail(e, "far-field re-check kernel");
+                r.qlive = qlive;
+            }
             e = launch_recheck(r, (a.jc1 - a.jc0) * pl.W, (p->flags & RS_EXACT_RECHECK) != 0, stream);
             if (e != hipSuccess) return hip_fail(e, "re-check kernel");
         }
@@ -366,6 +378,7 @@ int rs_read_stats(const void *workspace, rs_map_stats *stats_host, void *stream)
     stats_host->rays_out = c[C_OUT];
     stats_host->rays_singular = c[C_SING];
     stats_host->rays_rechecked = c[C_RECHECK];
+    stats_host->rays_rechecked_direct = c[C_DIRECT];
     stats_host->rays_shot = c[C_IN] + c[C_OUT] + c[C_SING];
     return RS_OK;
 }

@@ -249,6 +249,7 @@ void rs_server::retire_step(Step &s) {
         r.stats.rays_out += st[k].rays_out;
         r.stats.rays_singular += st[k].rays_singular;
         r.stats.rays_rechecked += st[k].rays_rechecked;
+        r.stats.rays_rechecked_direct += st[k].rays_rechecked_direct;
     }
     std::vector<Job> done = policy.step_done(s.slices, now_s());
     for (Job &j : done) {

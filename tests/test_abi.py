@@ -154,11 +154,14 @@ def test_farfield_mode_validation(lib):
     s = w.config0()
     c = api.to_params(s.params, "farfield")
     assert c.mode == L.RS_FARFIELD
-    # it needs the re-check queue of the mixed mode plus the super-patch records and lens lists
+    # it needs the re-check queue plus the super-patch records and lens lists; the mixed mode on
+    # the regular grid holds the same (its far-field re-check stage), its exact-only form does not
     mixed = api.workspace_bytes(s.params, s.n_lens, "mixed")
     ff = lib.rs_workspace_bytes(ctypes.byref(c), s.n_lens)
+    exact = lib.rs_workspace_bytes(ctypes.byref(api.to_params(s.params, "mixed", exact_recheck=True)), s.n_lens)
     n_super = -(-16 // 4) * -(-32 // 4)   # 1024^2 rays: 16 x 32 patches, 4 x 4 per super-patch
-    assert ff >= mixed + n_super * (36 * 8 + 4 * 4097)
+    assert ff == mixed
+    assert ff >= exact + n_super * (36 * 8 + 4 * 4097)
     p = dict(s.params)
     p.update(random_rays=1)
     assert lib.rs_workspace_bytes(ctypes.byref(api.to_params(p, "farfield")), s.n_lens) == 0

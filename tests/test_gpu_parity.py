@@ -224,6 +224,45 @@ def test_exact_only_recheck_matches_two_stage(rs):
     assert np.array_equal(pa, pb)
 
 
+def test_far_field_recheck_stage(rs):
+    """The mixed mode's first re-check stage (each queued ray from its super-patch's FP64
+    expansion plus the listed lenses) places almost every queued ray; the map and every ray's
+    pixel still equal the oracle's and the exact-only re-check's, with unit masses and with
+    masses."""
+    s = w.config2().window(4000, 5200, 1000, 1240)
+    rng = np.random.default_rng(21)
+    for masses in (None, rng.uniform(0.2, 1.8, size=s.n_lens)):
+        spec = w.MapSpec("far-recheck", s.params, s.lens_xy, masses)
+        m_o, _ = oracle.make_map(spec.params, spec.lens_xy, spec.lens_m)
+        a, sa = rs.make_map(spec.params, spec.lens_xy, spec.lens_m, mode="mixed", return_stats=True)
+        b, sb = rs.make_map(spec.params, spec.lens_xy, spec.lens_m, mode="mixed", return_stats=True,
+                            exact_recheck=True)
+        say(f"masses={masses is not None}: re-checked {sa['rays_rechecked']}, "
+            f"of which against every lens {sa['rays_rechecked_direct']}")
+        assert sa["rays_rechecked"] == sb["rays_rechecked"] > 1000
+        assert sb["rays_rechecked_direct"] == sb["rays_rechecked"]
+        assert sa["rays_rechecked_direct"] < 0.01 * sa["rays_rechecked"]
+        assert np.array_equal(a.cpu().numpy(), m_o) and np.array_equal(b.cpu().numpy(), m_o)
+        pix_o, _, _ = oracle.ray_pixels(spec.params, spec.lens_xy, spec.lens_m)
+        pa = rs.ray_pixels(spec.params, spec.lens_xy, spec.lens_m, mode="mixed").cpu().numpy()
+        assert np.array_equal(pa.astype(np.int64), pix_o)
+
+
+def test_far_field_recheck_list_overflow(rs):
+    """5000 light lenses inside four half-diagonals of every super-patch: the super-patch lists
+    overflow, the far-field stage places nothing, and the FP64 stages over every lens give the
+    oracle's map."""
+    rng = np.random.default_rng(22)
+    lens = w.lenses_in_disc(5000, 5.0, rng)
+    mm = rng.uniform(0.0005, 0.0015, size=5000)
+    p = w.make_params(0.064, 0.1, 0.2, (-3.0, -2.0, 6.0, 4.0, 300, 200), (-3.0, -2.0, 6.0, 4.0, 120, 80))
+    spec = w.MapSpec("overflow", p, lens, mm)
+    st = check_mixed_exact(rs, spec)
+    say(f"  re-checked {st['rays_rechecked']}, against every lens {st['rays_rechecked_direct']}")
+    assert st["rays_rechecked"] > 0
+    assert st["rays_rechecked_direct"] == st["rays_rechecked"]
+
+
 def test_every_shape_gives_the_same_maps(rs):
     """All thread shapes cover the same ray patch, so each ray's arithmetic is the same:
     FP32 maps are bit-identical across shapes, and mixed maps equal the oracle for every shape."""
