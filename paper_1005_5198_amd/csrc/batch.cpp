@@ -24,10 +24,21 @@ using namespace rs;
 
 extern "C" {
 
-// Workspace bytes: globals, descriptors, counters, and two bitmaps per map.
+// Per-map workspace after the counters: two bitmaps; in mixed mode also the
+// far-field re-check stage's super-patch records and lens lists.
+static size_t map_bytes(const rs_map_params &p) {
+    size_t b = 2 * 4 * (size_t)bitmap_words_of(p);
+    if (p.mode == RS_MIXED) {
+        const size_t ns = (size_t)super_patches_of(p);
+        b += align256(sizeof(double) * FF_REC_DOUBLES * ns) + align256(sizeof(int32_t) * (1 + FF_BATCH_CAP) * ns);
+    }
+    return b;
+}
+
+// Workspace bytes: globals, descriptors, counters, and the per-map parts.
 static size_t batch_bytes(const rs_map_request *reqs, int32_t n) {
     size_t off = batch_bitmaps_offset(n);
-    for (int32_t k = 0; k < n; ++k) off += 2 * 4 * (size_t)bitmap_words_of(reqs[k].params);
+    for (int32_t k = 0; k < n; ++k) off += map_bytes(reqs[k].params);
     return off;
 }
 
@@ -67,16 +78,16 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
 
     char *ws = static_cast<char *>(workspace);
     auto *counters = reinterpret_cast<unsigned long long *>(ws + batch_counters_offset(n));
-    std::vector<uint32_t *> bitmaps(n);
+    std::vector<char *> parts(n);
     {
         size_t off = batch_bitmaps_offset(n);
         for (int32_t k = 0; k < n; ++k) {
-            bitmaps[k] = reinterpret_cast<uint32_t *>(ws + off);
-            off += 2 * 4 * (size_t)bitmap_words_of(reqs[k].params);
+            parts[k] = ws + off;
+            off += map_bytes(reqs[k].params);
         }
     }
     std::vector<BatchMap> maps(n);
-    int64_t tiles = 0, words = 0;
+    int64_t tiles = 0, words = 0, supers = 0;
     double interactions = 0.0;
     bool unit = true;
     for (int32_t w = 0; w < n; ++w) {
@@ -95,8 +106,17 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
         m.tile_begin = tiles;
         m.n_words = bitmap_words_of(r.params);
         m.word_begin = words;
-        m.flag_bits = bitmaps[k];
-        m.unres_bits = bitmaps[k] + m.n_words;
+        m.flag_bits = reinterpret_cast<uint32_t *>(parts[k]);
+        m.unres_bits = m.flag_bits + m.n_words;
+        if (mode == RS_MIXED) {
+            m.n_super = super_patches_of(r.params);
+            m.ff_sbx = (((W + PATCH_X - 1) / PATCH_X) + FF_SP_X - 1) / FF_SP_X;
+            m.super_begin = supers;
+            char *rec = parts[k] + 2 * 4 * (size_t)m.n_words;
+            m.ff_super = reinterpret_cast<double *>(rec);
+            m.ff_near = reinterpret_cast<int32_t *>(rec + align256(sizeof(double) * FF_REC_DOUBLES * (size_t)m.n_super));
+            supers += m.n_super;
+        }
         m.request = k;
         m.accumulate = (r.params.flags & RS_ACCUMULATE) ? 1 : 0;
         if (r.lens_m != nullptr) unit = false;
@@ -116,6 +136,7 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
     b.unit_masses = unit ? 1 : 0;
     b.total_tiles = tiles;
     b.total_words = words;
+    b.total_super = supers;
     b.tile_counter = reinterpret_cast<unsigned long long *>(ws);
     b.unresolved = reinterpret_cast<unsigned int *>(ws + 8);
 
@@ -130,6 +151,8 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
     int rc = profile_end(s, tok, interactions);
     if (rc) return rc;
     if (mode == RS_MIXED) {
+        e = launch_batch_super(b, s);
+        if (e != hipSuccess) return hip_fail(e, "batched super-patch kernel");
         e = launch_recheck_batch(b, s);
         if (e != hipSuccess) return hip_fail(e, "batched re-check kernels");
     }
@@ -150,7 +173,7 @@ int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_ho
         stats_host[k].rays_out = q[C_OUT];
         stats_host[k].rays_singular = q[C_SING];
         stats_host[k].rays_rechecked = q[C_RECHECK];
-        stats_host[k].rays_rechecked_direct = q[C_RECHECK];   // a batch has no far-field stage
+        stats_host[k].rays_rechecked_direct = q[C_DIRECT];
         stats_host[k].rays_shot = q[C_IN] + q[C_OUT] + q[C_SING];
     }
     return RS_OK;

@@ -1,6 +1,6 @@
 // Far-field expansion (RS_FARFIELD): two levels of FP64 local expansions of the
 // distant lenses, near lenses summed directly, a rigorous per-ray bound.
-#include "shoot_common.h"
+#include "far_ray.h"
 
 namespace rs {
 namespace {
@@ -24,24 +24,10 @@ namespace {
 // definition's own rounding, and rays within it of a pixel edge go to the FP64
 // re-check, so the map equals the definition's.
 // ---------------------------------------------------------------------------
-constexpr int FAR_P = 16;
-constexpr double FAR_RATIO = 4.0;
 constexpr int FAR_THREADS = 256;
 constexpr int FAR_ROWS = PATCH_X * PATCH_Y / FAR_THREADS;     // rays per thread (8)
 static_assert(FAR_ROWS * (FAR_THREADS / 64) == (PATCH_X / 8) * (PATCH_Y / 8), "8 x 8 blocks cover the patch");
 constexpr int NEAR_EXP = 512;
-constexpr int FAR_EXTRA = 4;                                    // SFAR, TRUNC, SDEF, NFAR
-constexpr int FAR_REC = 2 * FAR_P + FAR_EXTRA;
-static_assert(FAR_REC == FF_REC_DOUBLES, "super-patch record size");
-
-__device__ __forceinline__ double rcp64(double r2) {
-    double rc = __builtin_amdgcn_rcp(r2);
-    double e = __builtin_fma(-r2, rc, 1.0);
-    rc = __builtin_fma(rc, e, rc);
-    e = __builtin_fma(-r2, rc, 1.0);
-    return __builtin_fma(rc, e, rc);
-}
-
 // One lens's contribution to an expansion about (ox, oy) with half-diagonal h
 // (the lens is at least FAR_RATIO h away): the powers m t^(n+1) and the bound
 // terms m/|d|, m/|d| rho^P / (1 - rho) and sqrt(2) m / (|d| - h).
@@ -116,53 +102,35 @@ struct FarAcc {
     }
 };
 
-// Geometry of super-patch sp of this launch: centre and half-diagonal (one ray
-// spacing of slack on each side), of the full box even where the window clips it.
-__device__ __forceinline__ void super_geometry(const ShootArgs &a, int64_t sp, double &cx, double &cy, double &H) {
-    const int64_t sx = sp % a.ff_sbx, sy = sp / a.ff_sbx;
-    const int64_t i_s = a.i0 + sx * (FF_SP_X * PATCH_X);
-    const int64_t j_s = a.jc0 + sy * (FF_SP_Y * PATCH_Y);
-    cx = a.sx0 + ((double)i_s + 0.5 * (FF_SP_X * PATCH_X)) * a.spx;
-    cy = a.sy0 + ((double)j_s + 0.5 * (FF_SP_Y * PATCH_Y)) * a.spy;
-    const double hx = (0.5 * (FF_SP_X * PATCH_X) + 1.0) * a.spx;
-    const double hy = (0.5 * (FF_SP_Y * PATCH_Y) + 1.0) * a.spy;
-    H = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
-}
-
 struct FarSuperSmem {
     double part[FAR_THREADS / 64][FAR_REC];
     double out[FAR_REC];
     int count;
 };
 
-// Level 1: one block per super-patch. Far lenses -> coefficients C about zS;
-// the others -> the super-patch's lens list (a count above FF_NEAR_CAP means
-// the list is incomplete and the patches scan every lens instead).
-// RECHECK: the mixed mode's re-check stage needs the records only when the
-// deflection launch queued rays.
-template <bool UNIT, bool RECHECK>
-__global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const ShootArgs a) {
-    __shared__ FarSuperSmem sm;
-    if (RECHECK && *a.qcount == 0) return;
-    const int64_t sp = blockIdx.x;
+// Records of super-patch sp: far lenses -> coefficients about zS; the others
+// -> the super-patch's lens list (a count above a.ff_cap means the list is
+// incomplete: the patches then scan every lens, the re-check stage passes).
+template <bool UNIT>
+__device__ inline void build_super(const ShootArgs &a, int64_t sp, FarSuperSmem &sm) {
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
     const double near_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
-    int32_t *list = a.ff_near + sp * (int64_t)(1 + FF_NEAR_CAP);
+    int32_t *list = a.ff_near + sp * (int64_t)(1 + a.ff_cap);
     if (threadIdx.x == 0) sm.count = 0;
     __syncthreads();
     FarAcc acc;
     acc.zero();
     for (int64_t k = threadIdx.x; k < a.n_lens; k += FAR_THREADS) {
-        const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
+        const double X = ((global_double *)a.lens_xy)[2 * k], Y = ((global_double *)a.lens_xy)[2 * k + 1];
         const double d1 = cx - X, d2 = cy - Y;
         const double r2 = d1 * d1 + d2 * d2;
         if (!(r2 >= near_r2)) {
             const int q = atomicAdd(&sm.count, 1);
-            if (q < FF_NEAR_CAP) list[1 + q] = (int32_t)k;
+            if (q < a.ff_cap) list[1 + q] = (int32_t)k;
             continue;
         }
-        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
+        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
         acc.add(d1, d2, r2, m, H);
     }
     acc.reduce(sm.part, sm.out);
@@ -171,36 +139,31 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const Shoot
     if (threadIdx.x == 0) list[0] = sm.count;
 }
 
-// Pixel decision of one ray from its FP64 deflection (a1, a2) = expansion +
-// directly summed lenses. Bound terms in source units: far_err (truncation and
-// rounding of the expansion), SFAR (sum of |m|/|d| over the expanded lenses,
-// which bounds the far sum by 1.34 SFAR), SDEF (the definition's rounding
-// weight of those lenses), snear and n_near (the direct sum, with its additions
-// onto the far sum), plus the definition's own lens-order rounding and the
-// epilogue. Returns the pixel, OUT, or FLAGGED.
-__device__ __forceinline__ int far_decide(const ShootArgs &a, double x1, double x2, double a1, double a2,
-                                          double far_err, double SFAR, double SDEF, double snear, int n_near,
-                                          bool sane_in) {
-    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
-    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
-    const double y1 = a.c1 * x1 - a1;
-    const double y2 = a.c2 * x2 - a2;
-    const double u = (y1 - a.tx0) * a.inv_pixw;
-    const double v = (y2 - a.ty0) * a.inv_pixh;
-    const double near_err = ((double)n_near + 10.0) * U64 * 1.001 * snear + (double)n_near * U64 * 1.34 * SFAR;
-    const double def_sum = kN * (snear + SDEF);
-    const double eu = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c1 * x1) + fabs(a1) + fabs(a.tx0));
-    const double ev = far_err + near_err + def_sum + 16.0 * U64 * (fabs(a.c2 * x2) + fabs(a2) + fabs(a.ty0));
-    const double Mu = 1.001 * eu * a.inv_pixw, Mv = 1.001 * ev * a.inv_pixh;
-    const double fu = floor(u), fv = floor(v);
-    const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
-    const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
-    const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
-    const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
-    const bool sane = sane_in && isfinite(Mu) && isfinite(Mv) && isfinite(u) && isfinite(v);
-    if (sane && ok_u && ok_v) return (int)((int64_t)fv * a.npx + (int64_t)fu);
-    if (sane && (out_u || out_v)) return OUT;
-    return FLAGGED;
+// Level 1 of one map: one block per super-patch. RECHECK: the mixed mode's
+// re-check stage needs the records only when the deflection launch queued rays.
+template <bool UNIT, bool RECHECK>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const ShootArgs a) {
+    __shared__ FarSuperSmem sm;
+    if (RECHECK && *a.qcount == 0) return;
+    build_super<UNIT>(a, blockIdx.x, sm);
+}
+
+// Level 1 of every map of a mixed batch that flagged rays: one block per
+// (map, super-patch), maps found by binary search on their first record.
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_THREADS) void batch_super_kernel(const BatchArgs b) {
+    __shared__ FarSuperSmem sm;
+    const int64_t t = blockIdx.x;
+    int lo = 0, hi = b.n_maps - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.maps[mid].super_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchMap &m = b.maps[lo];
+    if (t - m.super_begin >= m.n_super || m.counters[C_RECHECK] == 0ull) return;
+    const ShootArgs a = make_uniform(batch_far_args(m));
+    build_super<UNIT>(a, t - m.super_begin, sm);
 }
 
 struct FarSmem {
@@ -234,9 +197,9 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
     const double super_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
-    const int32_t *list = a.ff_near + sp * (int64_t)(1 + FF_NEAR_CAP);
+    const int32_t *list = a.ff_near + sp * (int64_t)(1 + a.ff_cap);
     const int32_t listed = list[0];
-    const bool scan_all = listed > FF_NEAR_CAP;
+    const bool scan_all = listed > a.ff_cap;
     if (tid == 0) sm.near_count = 0;
     if (tid < FAR_REC) sm.sc[tid] = a.ff_super[sp * (int64_t)FAR_REC + tid];
     __syncthreads();
@@ -363,16 +326,12 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a
 }
 
 // Re-check stage of the mixed mode on the regular grid, one thread per queued
-// ray: the ray's super-patch expansion (Horner in -w = zS - z, the same series
-// the patch kernel re-centres) plus the super-patch's listed lenses summed
-// directly in FP64, under the patch kernel's bound with no patch level. A ray
-// it places is binned and its entry marked RESOLVED; the others (a list over
-// FF_NEAR_CAP included) are counted in *qlive and left for the FP64 stage over
+// ray (far_recheck_ray). A ray it places is binned and its entry marked
+// RESOLVED; the others are counted in *qlive and left for the FP64 stage over
 // every lens. Queue entries of one deflection wave are adjacent and share a
 // super-patch, so a wave walks one list.
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_far_kernel(const ShootArgs a, uint32_t *qlive) {
-    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
     const uint32_t n = *a.qcount;
     const int64_t W = a.i1 - a.i0;
     unsigned long long n_in = 0, n_out = 0;
@@ -380,59 +339,17 @@ __global__ __launch_bounds__(256) void recheck_far_kernel(const ShootArgs a, uin
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
         const uint32_t q = a.queue[idx];
-        const int64_t ri = (int64_t)(q % (uint64_t)W), rj = (int64_t)(q / (uint64_t)W);
-        const int64_t i = a.i0 + ri, j = a.jc0 + rj;
-        const int64_t sp = (rj / (PATCH_Y * FF_SP_Y)) * a.ff_sbx + ri / (PATCH_X * FF_SP_X);
-        const int32_t *list = a.ff_near + sp * (int64_t)(1 + FF_NEAR_CAP);
-        const int32_t listed = list[0];
-        int code = FLAGGED;
-        if (listed <= FF_NEAR_CAP) {
-            const double *rec = a.ff_super + sp * (int64_t)FAR_REC;
-            double cx, cy, H;
-            super_geometry(a, sp, cx, cy, H);
-            const double x1 = ray_coord(a.sx0, i, a.spx);
-            const double x2 = ray_coord(a.sy0, j, a.spy);
-            const double nw1 = cx - x1, nw2 = cy - x2;   // -w
-            double S1 = rec[FAR_P - 1], S2 = rec[2 * FAR_P - 1];
-#pragma unroll
-            for (int nn = FAR_P - 2; nn >= 0; --nn) {
-                const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, rec[nn]));
-                const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, rec[FAR_P + nn]));
-                S1 = q1;
-                S2 = q2;
-            }
-            double a1 = S1, a2 = -S2;
-            double snear = 0.0;
-            bool tiny = false;
-            for (int l = 0; l < listed; ++l) {
-                const int64_t k = list[1 + l];
-                const double e1 = x1 - ((global_double *)a.lens_xy)[2 * k];
-                const double e2 = x2 - ((global_double *)a.lens_xy)[2 * k + 1];
-                const double r2 = __builtin_fma(e1, e1, e2 * e2);
-                tiny |= !(r2 > 1e-200);
-                const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
-                const double f = m * rcp64(r2);
-                a1 = __builtin_fma(f, e1, a1);
-                a2 = __builtin_fma(f, e2, a2);
-                snear = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), snear);
-            }
-            const double SFAR = rec[2 * FAR_P], TRUNC = rec[2 * FAR_P + 1], SDEF = rec[2 * FAR_P + 2];
-            const double NFAR = rec[2 * FAR_P + 3];
-            const double far_err = TRUNC + (NFAR + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR;
-            code = far_decide(a, x1, x2, a1, a2, far_err, SFAR, SDEF, snear, listed, !tiny);
-        }
+        const int64_t i = a.i0 + (int64_t)(q % (uint64_t)W);
+        const int64_t j = a.jc0 + (int64_t)(q / (uint64_t)W);
+        const int code = far_recheck_ray<UNIT>(a, i, j);
         if (code == FLAGGED) {
             ++left;
         } else {
             a.queue[idx] = q | RESOLVED;
-            if (code >= 0) {
-                ++n_in;
-                if (a.pix_out) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-                else atomicAdd(a.map + code, 1u);
-            } else {
-                ++n_out;
-                if (a.pix_out) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-            }
+            if (code >= 0) ++n_in;
+            else ++n_out;
+            if (a.pix_out) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+            else if (code >= 0) atomicAdd(a.map + code, 1u);
         }
     }
 #pragma unroll
@@ -464,6 +381,13 @@ hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_r
     if (blocks > 2048) blocks = 2048;
     if (unit) hipLaunchKernelGGL((recheck_far_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, stream, a, qlive);
     else hipLaunchKernelGGL((recheck_far_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, stream, a, qlive);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_super(const BatchArgs &b, hipStream_t stream) {
+    if (b.total_super <= 0) return hipSuccess;
+    if (b.unit_masses) hipLaunchKernelGGL((batch_super_kernel<true>), dim3((unsigned)b.total_super), dim3(FAR_THREADS), 0, stream, b);
+    else hipLaunchKernelGGL((batch_super_kernel<false>), dim3((unsigned)b.total_super), dim3(FAR_THREADS), 0, stream, b);
     return hipGetLastError();
 }
 

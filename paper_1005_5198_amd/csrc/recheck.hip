@@ -16,8 +16,8 @@
 // number left (*qlive).
 // Batch: the deflection kernel sets one bit per flagged ray in each map's
 // bitmap; a persistent scan compacts the set bits per wave and the map's
-// descriptor supplies its parameters.
-#include "recheck_ray.h"
+// descriptor supplies its parameters and its super-patch records (stage F).
+#include "far_ray.h"
 
 namespace rs {
 namespace {
@@ -223,6 +223,41 @@ __device__ inline void batch_stage_a(const BatchArgs &b, QueueEntry e, bool vali
     }
 }
 
+// Stage F for the entries held one per lane (valid lanes only), lanes grouped
+// by map as in stage A: each ray from its map's super-patch record and lens
+// list. Returns true in the lanes whose ray it placed; the others are counted
+// in their map's C_DIRECT and go on to stage A.
+template <bool ALL_UNIT>
+__device__ inline bool batch_stage_f(const BatchArgs &b, QueueEntry e, bool valid) {
+    bool placed = false;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t mi = (uint32_t)__builtin_amdgcn_readlane((int)e.map, leader);
+        const bool mine = valid && e.map == mi;
+        pending &= ~__ballot(mine);
+        const ShootArgs a = make_uniform(batch_far_args(b.maps[mi]));
+        int code = FLAGGED;
+        if (mine) {
+            const int64_t W = a.i1 - a.i0;
+            const int64_t i = a.i0 + (int64_t)(e.ray % (uint64_t)W);
+            const int64_t j = a.j0 + (int64_t)(e.ray / (uint64_t)W);
+            code = (ALL_UNIT || a.lens_m == nullptr) ? far_recheck_ray<true>(a, i, j) : far_recheck_ray<false>(a, i, j);
+            if (code >= 0) atomicAdd(a.map + code, 1u);
+            placed = code != FLAGGED;
+        }
+        const unsigned n_in = (unsigned)__builtin_popcountll(__ballot(mine && code >= 0));
+        const unsigned n_out = (unsigned)__builtin_popcountll(__ballot(mine && code == OUT));
+        const unsigned n_left = (unsigned)__builtin_popcountll(__ballot(mine && code == FLAGGED));
+        if (__lane_id() == leader) {
+            if (n_in) atomicAdd(a.counters + C_IN, (unsigned long long)n_in);
+            if (n_out) atomicAdd(a.counters + C_OUT, (unsigned long long)n_out);
+            if (n_left) atomicAdd(a.counters + C_DIRECT, (unsigned long long)n_left);
+        }
+    }
+    return placed;
+}
+
 // Exact stage for up to 64 entries held one per lane: one wave per ray.
 // Stage A of one queued ray (wave-uniform entry) by the whole wave: lanes split the
 // lenses. Used for a wave's last few rays, where one ray per lane would leave the
@@ -262,8 +297,8 @@ __device__ inline void batch_stage_b(const BatchArgs &b, QueueEntry e, int n_val
     }
 }
 
-// Persistent scan of the batch's bitmaps (STAGE 0: flag bits -> stage A;
-// STAGE 1: unresolved bits -> exact stage). The batch's words are dealt to the
+// Persistent scan of the batch's bitmaps (STAGE 0: flag bits -> stage F, then
+// stage A for the rays it leaves; STAGE 1: unresolved bits -> exact stage). The batch's words are dealt to the
 // waves one at a time (lane l of wave k reads word k + (t + l) n_waves), so a
 // dense run of flagged rays - a crowded lens region fills whole rows of them -
 // is spread over many waves instead of queueing in one. Each wave compacts its
@@ -311,7 +346,10 @@ __global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs
                 const QueueEntry e = ring[(head + lane) % RING];
                 head += 64;
                 wave_sync();
-                if (STAGE == 0) batch_stage_a<ALL_UNIT>(b, e, true);
+                if (STAGE == 0) {
+                    const bool placed = batch_stage_f<ALL_UNIT>(b, e, true);
+                    batch_stage_a<ALL_UNIT>(b, e, !placed);
+                }
                 else batch_stage_b(b, e, 64);
             }
         }
@@ -321,8 +359,13 @@ __global__ __launch_bounds__(256) void recheck_scan_batch_kernel(const BatchArgs
         QueueEntry e{0u, 0u};
         if (lane < left) e = ring[(head + lane) % RING];
         if (STAGE == 0) {
-            // the last few rays: one wave per ray (lenses split over the lanes)
-            for (int s = 0; s < left; ++s) {
+            // the last few rays: stage F one per lane, then stage A one wave per ray
+            // (lenses split over the lanes) for those it could not place
+            const bool placed = batch_stage_f<ALL_UNIT>(b, e, lane < left);
+            uint64_t rest = __ballot(lane < left && !placed);
+            while (rest) {
+                const int s = __builtin_ctzll(rest);
+                rest &= rest - 1;
                 QueueEntry es;
                 es.map = (uint32_t)__builtin_amdgcn_readlane((int)e.map, s);
                 es.ray = (uint32_t)__builtin_amdgcn_readlane((int)e.ray, s);

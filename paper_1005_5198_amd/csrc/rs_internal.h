@@ -77,12 +77,14 @@ struct ShootArgs {
     // Far-field expansion (RS_FARFIELD): super-patches of FF_SP_X x FF_SP_Y patches.
     int64_t ff_sbx;        // super-patches along x in this launch
     double *ff_super;      // [n_super][2 * 16 + 4] coefficients and bound terms
-    int32_t *ff_near;      // [n_super][1 + FF_NEAR_CAP] count, then indices of the nearer lenses
+    int32_t *ff_near;      // [n_super][1 + ff_cap] count, then indices of the nearer lenses
+    int32_t ff_cap;        // list capacity per super-patch
 };
 
 constexpr int FF_SP_X = 4;
 constexpr int FF_SP_Y = 4;
-constexpr int FF_NEAR_CAP = 4096;
+constexpr int FF_NEAR_CAP = 4096;    // single maps (the far-field mode rescans all lenses beyond it)
+constexpr int FF_BATCH_CAP = 1024;   // batches (the re-check stage only; beyond it, the stage over every lens)
 constexpr int FF_REC_DOUBLES = 36;
 
 // Random rays: expected rays per bin (a block's capacity is 2048, so a bin
@@ -202,6 +204,12 @@ struct BatchMap {
     int64_t n_words;               // bitmap words, a multiple of 64
     int32_t request;               // index of the request this map came from
     int32_t accumulate;            // keep the map's contents (RS_ACCUMULATE)
+    // Mixed mode: the far-field re-check stage's super-patch records of the window.
+    int64_t ff_sbx;                // super-patches along x
+    int64_t super_begin;           // first record of this map in the batch's record space
+    int64_t n_super;
+    double *ff_super;              // [n_super][FF_REC_DOUBLES]
+    int32_t *ff_near;              // [n_super][1 + FF_BATCH_CAP]
 };
 
 struct QueueEntry {
@@ -217,13 +225,15 @@ struct BatchArgs {
     int32_t pad;
     int64_t total_tiles;
     int64_t total_words;
+    int64_t total_super;           // super-patch records of every map (mixed mode)
     unsigned long long *tile_counter;
     unsigned int *unresolved;          // set when stage A left a ray to the exact stage
 };
 
 // Batch workspace layout (bytes):
 //   [globals 256: uint64 tile counter, uint32 unresolved flag]
-//   [BatchMap x n][counters 64 x n][flag bitmaps][unresolved bitmaps]
+//   [BatchMap x n][counters 64 x n][per map: flag bitmap, unresolved bitmap;
+//    mixed mode: super-patch records, lens lists]
 constexpr size_t BWS_GLOBALS = 256;
 constexpr int64_t BITMAP_WORD_ALIGN = 64;   // a 64-word scan block never straddles two maps
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -231,6 +241,10 @@ inline size_t batch_maps_offset() { return BWS_GLOBALS; }
 inline size_t batch_counters_offset(int32_t n) { return align256(BWS_GLOBALS + sizeof(BatchMap) * (size_t)n); }
 inline size_t batch_bitmaps_offset(int32_t n) {
     return align256(batch_counters_offset(n) + sizeof(unsigned long long) * N_COUNTERS * (size_t)n);
+}
+inline int64_t super_patches_of(const rs_map_params &p) {
+    const int64_t nbx = (p.i1 - p.i0 + PATCH_X - 1) / PATCH_X, nby = (p.j1 - p.j0 + PATCH_Y - 1) / PATCH_Y;
+    return ((nbx + FF_SP_X - 1) / FF_SP_X) * ((nby + FF_SP_Y - 1) / FF_SP_Y);
 }
 inline int64_t bitmap_words_of(const rs_map_params &p) {
     const int64_t rays = (p.i1 - p.i0) * (p.j1 - p.j0);
@@ -255,5 +269,7 @@ hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_r
 hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream);
 hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream);
 hipError_t launch_recheck_batch(const BatchArgs &b, hipStream_t stream);
+// Mixed batches: super-patch records of every map that flagged rays.
+hipError_t launch_batch_super(const BatchArgs &b, hipStream_t stream);
 
 }  // namespace rs

@@ -276,6 +276,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         a.ff_sbx = (a.nbx + FF_SP_X - 1) / FF_SP_X;
         a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
         a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
+        a.ff_cap = FF_NEAR_CAP;
     }
     if (shape < 0 && !pl.random && p->mode != RS_FARFIELD) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
     hipEvent_t t_first = nullptr, t_last = nullptr;

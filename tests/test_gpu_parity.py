@@ -263,6 +263,27 @@ def test_far_field_recheck_list_overflow(rs):
     assert st["rays_rechecked_direct"] == st["rays_rechecked"]
 
 
+def test_batch_far_field_stage_list_overflow(rs):
+    """A batch whose first map's super-patch lists overflow (5000 lenses within reach of every
+    super-patch) next to an ordinary map: the overflowing map's flagged rays all take the stage
+    over every lens, the other map's almost none, and both maps equal the oracle's."""
+    rng = np.random.default_rng(23)
+    lens = w.lenses_in_disc(5000, 5.0, rng)
+    mm = rng.uniform(0.0005, 0.0015, size=5000)
+    dense = w.MapSpec("overflow", w.make_params(0.064, 0.1, 0.2, (-3.0, -2.0, 6.0, 4.0, 300, 200),
+                                                (-3.0, -2.0, 6.0, 4.0, 120, 80)), lens, mm)
+    plain = w.config2().window(2000, 2900, 600, 800)
+    outs, stats = rs.make_maps([(x.params, x.lens_xy, x.lens_m) for x in (dense, plain)], mode="mixed",
+                               return_stats=True)
+    for x, o, st in zip((dense, plain), outs, stats):
+        say("batch", x.name, st)
+        m_o, _ = oracle.make_map(x.params, x.lens_xy, x.lens_m)
+        assert np.array_equal(o.cpu().numpy(), m_o), x.name
+    assert stats[0]["rays_rechecked"] > 0 and stats[0]["rays_rechecked_direct"] == stats[0]["rays_rechecked"]
+    assert stats[1]["rays_rechecked"] > 1000
+    assert stats[1]["rays_rechecked_direct"] < 0.02 * stats[1]["rays_rechecked"]
+
+
 def test_every_shape_gives_the_same_maps(rs):
     """All thread shapes cover the same ray patch, so each ray's arithmetic is the same:
     FP32 maps are bit-identical across shapes, and mixed maps equal the oracle for every shape."""
@@ -328,6 +349,10 @@ def test_batch_matches_single_and_oracle(rs):
                 # a batch mixing unit and general masses bounds unit-mass maps with the general
                 # constant, so it may re-check more rays; the maps stay identical
                 assert st["rays_rechecked"] >= st1["rays_rechecked"]
+                # the far-field stage places almost every flagged ray in a batch too
+                assert st["rays_rechecked_direct"] <= st["rays_rechecked"]
+                if st["rays_rechecked"] > 1000:
+                    assert st["rays_rechecked_direct"] < 0.02 * st["rays_rechecked"], s.name
                 if s.n_rays * s.n_lens < 3e9:
                     m_o, _ = oracle.make_map(s.params, s.lens_xy, s.lens_m)
                     assert np.array_equal(o.cpu().numpy(), m_o)
