@@ -24,12 +24,12 @@ __device__ __forceinline__ double rcp64(double r2) {
     return __builtin_fma(rc, e, rc);
 }
 
-// Geometry of super-patch sp of this launch: centre and half-diagonal (one ray
-// spacing of slack on each side), of the full box even where the window clips it.
+// Geometry of super-patch sp: centre and half-diagonal (one ray spacing of
+// slack on each side), of the full box even where the window clips it.
 __device__ __forceinline__ void super_geometry(const ShootArgs &a, int64_t sp, double &cx, double &cy, double &H) {
     const int64_t sx = sp % a.ff_sbx, sy = sp / a.ff_sbx;
-    const int64_t i_s = a.i0 + sx * (FF_SP_X * PATCH_X);
-    const int64_t j_s = a.jc0 + sy * (FF_SP_Y * PATCH_Y);
+    const int64_t i_s = a.ff_i0 + sx * (FF_SP_X * PATCH_X);
+    const int64_t j_s = a.ff_j0 + sy * (FF_SP_Y * PATCH_Y);
     cx = a.sx0 + ((double)i_s + 0.5 * (FF_SP_X * PATCH_X)) * a.spx;
     cy = a.sy0 + ((double)j_s + 0.5 * (FF_SP_Y * PATCH_Y)) * a.spy;
     const double hx = (0.5 * (FF_SP_X * PATCH_X) + 1.0) * a.spx;
@@ -73,31 +73,29 @@ __device__ __forceinline__ int far_decide(const ShootArgs &a, double x1, double 
 __device__ inline ShootArgs batch_far_args(const BatchMap &m) {
     ShootArgs a = shoot_args_of(m.p, m.lens_xy, m.lens_m, m.n_lens, m.map, m.counters);
     a.ff_sbx = m.ff_sbx;
+    a.ff_i0 = m.p.i0;
+    a.ff_j0 = m.p.j0;
     a.ff_super = m.ff_super;
     a.ff_near = m.ff_near;
     a.ff_cap = FF_BATCH_CAP;
     return a;
 }
 
-// Re-check stage F for one ray (i, j) of the launch: its super-patch's series
-// (Horner in -w = zS - z, the series the patch kernel re-centres) plus the
-// super-patch's listed lenses summed directly in FP64, under the patch
+// Re-check stage F for one ray at (x1, x2) inside super-patch sp: the
+// super-patch's series (Horner in -w = zS - z, the series the patch kernel
+// re-centres) plus its listed lenses summed directly in FP64, under the patch
 // kernel's bound with no patch level. Returns the definition's pixel or OUT,
 // or FLAGGED when the bound reaches a pixel edge, the ray sits on a listed
 // lens, or the list overflowed.
 template <bool UNIT>
-__device__ inline int far_recheck_ray(const ShootArgs &a, int64_t i, int64_t j) {
+__device__ inline int far_eval(const ShootArgs &a, int64_t sp, double x1, double x2) {
     constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
-    const int64_t ri = i - a.i0, rj = j - a.jc0;
-    const int64_t sp = (rj / (PATCH_Y * FF_SP_Y)) * a.ff_sbx + ri / (PATCH_X * FF_SP_X);
     const int32_t *list = a.ff_near + sp * (int64_t)(1 + a.ff_cap);
     const int32_t listed = list[0];
     if (listed > a.ff_cap) return FLAGGED;
     const double *rec = a.ff_super + sp * (int64_t)FAR_REC;
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
-    const double x1 = ray_coord(a.sx0, i, a.spx);
-    const double x2 = ray_coord(a.sy0, j, a.spy);
     const double nw1 = cx - x1, nw2 = cy - x2;   // -w
     double S1 = rec[FAR_P - 1], S2 = rec[2 * FAR_P - 1];
 #pragma unroll
@@ -126,6 +124,29 @@ __device__ inline int far_recheck_ray(const ShootArgs &a, int64_t i, int64_t j) 
     const double NFAR = rec[2 * FAR_P + 3];
     const double far_err = TRUNC + (NFAR + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR;
     return far_decide(a, x1, x2, a1, a2, far_err, SFAR, SDEF, snear, listed, !tiny);
+}
+
+// Stage F for ray (i, j): on the grid its super-patch follows from its indices;
+// a random ray's from its position (the cell of the whole rectangle's
+// super-patch grid that holds it, clamped: a ray within rounding of a cell
+// edge is still inside the neighbouring box's one-spacing slack).
+template <bool UNIT>
+__device__ inline int far_recheck_ray(const ShootArgs &a, int64_t i, int64_t j) {
+    double x1, x2;
+    int64_t sp;
+    if (a.random) {
+        random_ray_xy(a.sx0, a.sy0, a.sw, a.sh, a.nx, a.seed, i, j, x1, x2);
+        int64_t sx = (int64_t)floor((x1 - a.sx0) / ((double)(FF_SP_X * PATCH_X) * a.spx));
+        int64_t sy = (int64_t)floor((x2 - a.sy0) / ((double)(FF_SP_Y * PATCH_Y) * a.spy));
+        sx = sx < 0 ? 0 : (sx >= a.ff_sbx ? a.ff_sbx - 1 : sx);
+        sy = sy < 0 ? 0 : (sy >= a.ff_sby ? a.ff_sby - 1 : sy);
+        sp = sy * a.ff_sbx + sx;
+    } else {
+        x1 = ray_coord(a.sx0, i, a.spx);
+        x2 = ray_coord(a.sy0, j, a.spy);
+        sp = ((j - a.ff_j0) / (PATCH_Y * FF_SP_Y)) * a.ff_sbx + (i - a.ff_i0) / (PATCH_X * FF_SP_X);
+    }
+    return far_eval<UNIT>(a, sp, x1, x2);
 }
 
 }  // namespace

@@ -139,8 +139,9 @@ __device__ inline void build_super(const ShootArgs &a, int64_t sp, FarSuperSmem 
     if (threadIdx.x == 0) list[0] = sm.count;
 }
 
-// Level 1 of one map: one block per super-patch. RECHECK: the mixed mode's
-// re-check stage needs the records only when the deflection launch queued rays.
+// Level 1 of one launch (or, for random rays, of the whole rectangle): one block
+// per super-patch. RECHECK: the grid re-check stage needs the records only when
+// the deflection launch queued rays.
 template <bool UNIT, bool RECHECK>
 __global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const ShootArgs a) {
     __shared__ FarSuperSmem sm;
@@ -368,19 +369,29 @@ __global__ __launch_bounds__(256) void recheck_far_kernel(const ShootArgs a, uin
 }  // namespace
 
 hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_rays, hipStream_t stream) {
-    const int64_t rows = a.jc1 - a.jc0;
-    const int64_t nby = (rows + PATCH_Y - 1) / PATCH_Y;
-    const int64_t n_super = a.ff_sbx * ((nby + FF_SP_Y - 1) / FF_SP_Y);
-    if (n_super <= 0 || max_rays <= 0) return hipSuccess;
+    if (max_rays <= 0) return hipSuccess;
     const bool unit = a.lens_m == nullptr;
-    if (unit) hipLaunchKernelGGL((farfield_super_kernel<true, true>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
-    else hipLaunchKernelGGL((farfield_super_kernel<false, true>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!a.random) {   // grid: this launch's records (random rays: the map's, built once)
+        const int64_t rows = a.jc1 - a.jc0;
+        const int64_t nby = (rows + PATCH_Y - 1) / PATCH_Y;
+        const int64_t n_super = a.ff_sbx * ((nby + FF_SP_Y - 1) / FF_SP_Y);
+        if (n_super <= 0) return hipSuccess;
+        if (unit) hipLaunchKernelGGL((farfield_super_kernel<true, true>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
+        else hipLaunchKernelGGL((farfield_super_kernel<false, true>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     int64_t blocks = (max_rays + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     if (unit) hipLaunchKernelGGL((recheck_far_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, stream, a, qlive);
     else hipLaunchKernelGGL((recheck_far_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, stream, a, qlive);
+    return hipGetLastError();
+}
+
+hipError_t launch_super_records(const ShootArgs &a, int64_t n_super, hipStream_t stream) {
+    if (n_super <= 0) return hipSuccess;
+    if (a.lens_m == nullptr) hipLaunchKernelGGL((farfield_super_kernel<true, false>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
+    else hipLaunchKernelGGL((farfield_super_kernel<false, false>), dim3((unsigned)n_super), dim3(FAR_THREADS), 0, stream, a);
     return hipGetLastError();
 }
 

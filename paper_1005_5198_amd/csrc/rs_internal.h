@@ -76,6 +76,9 @@ struct ShootArgs {
     double *ray_x, *ray_y; // [rays] FP64 positions, same order
     // Far-field expansion (RS_FARFIELD): super-patches of FF_SP_X x FF_SP_Y patches.
     int64_t ff_sbx;        // super-patches along x in this launch
+    int64_t ff_sby;        // super-patches along y (random rays: a ray's cell is clamped to it)
+    int64_t ff_i0, ff_j0;  // ray-grid origin of super-patch 0: the launch's (i0, jc0), or (0, 0)
+                           // for random rays, whose records cover the whole shooting rectangle
     double *ff_super;      // [n_super][2 * 16 + 4] coefficients and bound terms
     int32_t *ff_near;      // [n_super][1 + ff_cap] count, then indices of the nearer lenses
     int32_t ff_cap;        // list capacity per super-patch
@@ -265,6 +268,9 @@ hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_onl
 // the far-field re-check stage over the queue (a.queue, a.qcount); it counts the
 // entries it leaves undecided in *qlive.
 hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_rays, hipStream_t stream);
+// Records of n_super super-patches from origin (a.ff_i0, a.ff_j0), unconditionally
+// (random rays: the whole rectangle, once per map).
+hipError_t launch_super_records(const ShootArgs &a, int64_t n_super, hipStream_t stream);
 
 hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream);
 hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream);

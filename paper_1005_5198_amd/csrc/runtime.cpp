@@ -35,7 +35,8 @@ struct Plan {
     int64_t rows_per_chunk = 0, n_chunks = 0;
     int64_t queue_cap = 0;   // uint32 entries (mixed only)
     size_t qcount_bytes = 0; // WS_QCOUNT + 8 * n_chunks (queue lengths, live counts), 256-aligned
-    bool far_recheck = false; // mixed mode on the regular grid: far-field re-check stage first
+    bool far_recheck = false; // mixed mode: far-field re-check stage first
+    int64_t rand_sbx = 0, rand_sby = 0; // random rays: super-patch grid of the whole rectangle
     // Random rays: bin arrays for the largest number of bins of a launch, and
     // the sorted ray list (index, x, y) of the largest launch.
     bool random = false;
@@ -106,11 +107,20 @@ Plan make_plan(const rs_map_params *p) {
     pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
     pl.qcount_bytes = (WS_QCOUNT + 8 * (size_t)pl.n_chunks + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
-    pl.far_recheck = p->mode == RS_MIXED && !pl.random && !(p->flags & RS_EXACT_RECHECK);
+    pl.far_recheck = p->mode == RS_MIXED && !(p->flags & RS_EXACT_RECHECK);
+    if (pl.far_recheck && pl.random) {
+        // Random rays land anywhere in the shooting rectangle, so the records cover all
+        // of it, built once per map; used unless the window holds few of its rays.
+        pl.rand_sbx = (p->nx + FF_SP_X * PATCH_X - 1) / (FF_SP_X * PATCH_X);
+        pl.rand_sby = (p->ny + FF_SP_Y * PATCH_Y - 1) / (FF_SP_Y * PATCH_Y);
+        const int64_t own = (pl.W * pl.H + FF_SP_X * PATCH_X * FF_SP_Y * PATCH_Y - 1) / (FF_SP_X * PATCH_X * FF_SP_Y * PATCH_Y);
+        if (pl.rand_sbx * pl.rand_sby > 4 * own + 64) pl.far_recheck = false;
+    }
     if ((p->mode == RS_FARFIELD || pl.far_recheck) && pl.n_chunks > 0) {
         const int64_t nbx = (pl.W + PATCH_X - 1) / PATCH_X;
         const int64_t nby = (rows_cap + PATCH_Y - 1) / PATCH_Y;
-        pl.super_cap = ((nbx + FF_SP_X - 1) / FF_SP_X) * ((nby + FF_SP_Y - 1) / FF_SP_Y);
+        pl.super_cap = pl.random ? pl.rand_sbx * pl.rand_sby
+                                 : ((nbx + FF_SP_X - 1) / FF_SP_X) * ((nby + FF_SP_Y - 1) / FF_SP_Y);
         size_t off = a256(pl.bytes);
         pl.ff_super_off = off;
         off += a256(sizeof(double) * FF_REC_DOUBLES * (size_t)pl.super_cap);
@@ -272,11 +282,18 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         a.ray_y = reinterpret_cast<double *>(ws + pl.y_off);
     }
 
-    if (p->mode == RS_FARFIELD || pl.far_recheck) {
-        a.ff_sbx = (a.nbx + FF_SP_X - 1) / FF_SP_X;
+    if ((p->mode == RS_FARFIELD || pl.far_recheck) && pl.n_chunks > 0) {
+        a.ff_sbx = pl.random ? pl.rand_sbx : (a.nbx + FF_SP_X - 1) / FF_SP_X;
+        a.ff_sby = pl.rand_sby;
         a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
         a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
         a.ff_cap = FF_NEAR_CAP;
+        if (pl.random) {
+            a.ff_i0 = 0;
+            a.ff_j0 = 0;
+            e = launch_super_records(a, pl.super_cap, stream);
+            if (e != hipSuccess) return hip_fail(e, "super-patch records");
+        }
     }
     if (shape < 0 && !pl.random && p->mode != RS_FARFIELD) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
     hipEvent_t t_first = nullptr, t_last = nullptr;
@@ -290,6 +307,10 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         a.jc0 = p->j0 + c * pl.rows_per_chunk;
         a.jc1 = a.jc0 + pl.rows_per_chunk < p->j1 ? a.jc0 + pl.rows_per_chunk : p->j1;
         a.qcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + c;
+        if (!pl.random) {   // grid super-patches start at this launch's first patch
+            a.ff_i0 = a.i0;
+            a.ff_j0 = a.jc0;
+        }
         void *tok = nullptr;
         profile_begin(stream, &tok);
         if (kernel_ms && hipEventRecord(t_first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");

@@ -119,7 +119,11 @@ def test_config2_full_map_sampled(rs):
     assert st["rays_in_map"] + st["rays_out"] + st["rays_singular"] == s.n_rays
     assert int(a.sum()) == st["rays_in_map"]
     say(f"  in-map {st['rays_in_map']}, re-checked {st['rays_rechecked']} "
-        f"({st['rays_rechecked'] / s.n_rays:.3%})")
+        f"({st['rays_rechecked'] / s.n_rays:.3%}), against every lens {st['rays_rechecked_direct']}")
+    # the whole map equals the one whose flagged rays all take the definition's exact sequence
+    exact = rs.make_map(s.params, xy, None, mode="mixed", exact_recheck=True)
+    assert torch.equal(out1, exact)
+    assert st["rays_rechecked_direct"] < 0.02 * st["rays_rechecked"]
     # sampled rays: a 64 x 16 window at seeded random places, each ray vs the oracle
     rng = np.random.default_rng(7)
     for _ in range(6):

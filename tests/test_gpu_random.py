@@ -123,7 +123,12 @@ def test_random_config2_full_map(rs):
     b = rs.make_map(s.params, xy, None, mode="mixed", workspace=ws)
     assert torch.equal(a, b) and rs.read_stats(ws) == st
     assert st["rays_in_map"] + st["rays_out"] + st["rays_singular"] == s.n_rays
-    say(f"  re-checked {st['rays_rechecked'] / s.n_rays:.3%}")
+    say(f"  re-checked {st['rays_rechecked'] / s.n_rays:.3%}, against every lens {st['rays_rechecked_direct']}")
+    # the far-field stage (records of the whole rectangle, cells found by position) places
+    # almost every flagged ray, and the map equals the one re-checked with the exact sequence only
+    assert st["rays_rechecked_direct"] < 0.02 * st["rays_rechecked"]
+    exact, st_x = rs.make_map(s.params, xy, None, mode="mixed", return_stats=True, exact_recheck=True)
+    assert torch.equal(a, exact) and st_x["rays_rechecked_direct"] == st_x["rays_rechecked"] == st["rays_rechecked"]
     rng = np.random.default_rng(8)
     for _ in range(4):
         i0 = int(rng.integers(0, 19200 - 64))
