@@ -178,7 +178,7 @@ struct FarSmem {
 
 // Level 2: one block per patch.
 template <bool UNIT, bool PIX>
-__global__ __launch_bounds__(FAR_THREADS) void farfield_kernel(const ShootArgs a) {
+__global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArgs a) {
     __shared__ FarSmem sm;
     constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
     const int tid = threadIdx.x;

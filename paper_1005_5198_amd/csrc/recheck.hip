@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void recheck_fast_kernel(const RecheckArgs a) 
             place(a, i, j, code);
         } else {
             a.queue[idx] = q | UNRESOLVED;
+            if (a.qunres) atomicAdd(a.qunres, 1u);
         }
     }
     count_wave(a.counters, n_in, n_out, n_sing);
@@ -137,6 +138,7 @@ __global__ __launch_bounds__(256) void recheck_fast_wave_kernel(const RecheckArg
                     place(a, i, j, code);
                 } else {
                     a.queue[idx64] = q | UNRESOLVED;
+                    if (a.qunres) atomicAdd(a.qunres, 1u);
                 }
             }
         }
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(256) void recheck_fast_wave_kernel(const RecheckArg
 
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_exact_wave_kernel(const RecheckArgs a) {
+    if (a.qunres && *a.qunres == 0u) return;   // stage A decided every entry
     const uint32_t n = *a.qcount;
     const int64_t W = a.i1 - a.i0;
     const int lane = __lane_id();

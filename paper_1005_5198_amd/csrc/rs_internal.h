@@ -25,12 +25,12 @@ const ShapeInfo &shape_info(int shape);
 // Lenses staged into LDS per tile, and lenses per FP32 partial sum before it
 // is folded into the FP64 accumulator.
 constexpr int LENS_TILE = 1024;
-constexpr int GROUP = 16;
+constexpr int GROUP = 32;
 constexpr int NEAR_MAX = 64;                  // per-block list of lenses close to the patch
 
 // Workspace layout (bytes).
 constexpr size_t WS_COUNTERS = 0;             // uint64 [8]: in, out, singular, rechecked, spare
-constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] queue lengths, then [n_chunks] live counts
+constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] each: queue lengths, live counts, unresolved counts
 constexpr int64_t CHUNK_RAYS = int64_t(1) << 27;  // rays per launch (queue capacity)
 
 enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3, C_DIRECT = 4 };
@@ -112,6 +112,7 @@ struct RecheckArgs {
     uint32_t *queue;       // stage A marks unresolved entries in place
     const uint32_t *qcount;
     const uint32_t *qlive; // entries the far-field stage left undecided, or nullptr (no such stage)
+    uint32_t *qunres;      // entries stage A left to the exact stage (counted by stage A), or nullptr
     int32_t random;        // Philox-random ray positions (RS_RANDOM_RAYS)
     uint64_t seed;
 };

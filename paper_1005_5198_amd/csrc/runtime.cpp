@@ -34,7 +34,7 @@ struct Plan {
     int64_t W = 0, H = 0;
     int64_t rows_per_chunk = 0, n_chunks = 0;
     int64_t queue_cap = 0;   // uint32 entries (mixed only)
-    size_t qcount_bytes = 0; // WS_QCOUNT + 8 * n_chunks (queue lengths, live counts), 256-aligned
+    size_t qcount_bytes = 0; // WS_QCOUNT + 12 * n_chunks (queue lengths, live and unresolved counts), 256-aligned
     bool far_recheck = false; // mixed mode: far-field re-check stage first
     int64_t rand_sbx = 0, rand_sby = 0; // random rays: super-patch grid of the whole rectangle
     // Random rays: bin arrays for the largest number of bins of a launch, and
@@ -105,7 +105,7 @@ Plan make_plan(const rs_map_params *p) {
     pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
     const int64_t rows_cap = pl.H < rows ? pl.H : rows;
     pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
-    pl.qcount_bytes = (WS_QCOUNT + 8 * (size_t)pl.n_chunks + 255) / 256 * 256;
+    pl.qcount_bytes = (WS_QCOUNT + 12 * (size_t)pl.n_chunks + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
     pl.far_recheck = p->mode == RS_MIXED && !(p->flags & RS_EXACT_RECHECK);
     if (pl.far_recheck && pl.random) {
@@ -211,7 +211,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
 
     const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
     hipError_t e =
-        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 2 * pl.n_chunks, stream);
+        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 3 * pl.n_chunks, stream);
     if (e != hipSuccess) return hip_fail(e, "fill kernel");
 
     char *ws = static_cast<char *>(workspace);
@@ -340,6 +340,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
             r.jc0 = a.jc0;
             r.qcount = a.qcount;
             r.qlive = nullptr;
+            r.qunres = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 2 * pl.n_chunks + c;
             if (pl.far_recheck) {
                 uint32_t *qlive = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + pl.n_chunks + c;
                 e = launch_recheck_far(a, qlive, (a.jc1 - a.jc0) * pl.W, stream);
