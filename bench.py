@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-farfield", action="store_true", help="skip the far-field expansion mode timing")
     ap.add_argument("--no-tune", action="store_true", help="keep the default thread shape (skip the autotuner)")
     ap.add_argument("--no-random", action="store_true", help="skip the random-ray map timing")
+    ap.add_argument("--no-other-maps", action="store_true",
+                    help="skip the 32768^2-ray map and the paper's sigma=0.4 point (each mode)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-rho", type=float, default=0.8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -95,9 +97,29 @@ def cpu_baseline(spec, target_s: float):
     t = time.perf_counter()
     oracle.make_map(sub.params, sub.lens_xy, sub.lens_m, nthreads=threads)
     dt = time.perf_counter() - t
+    # the whole 1024^2-ray, 462-lens map on one core
+    from paper_1005_5198_amd import workloads as w
+    c0 = w.config0()
+    t = time.perf_counter()
+    oracle.make_map(c0.params, c0.lens_xy, c0.lens_m, nthreads=1)
+    dt0 = time.perf_counter() - t
     return {"value": sub.interactions / dt, "unit": "ray·lens/s", "cores": threads, "kind": "oracle",
             "sample": f"rows {j0}..{j0 + rows} of the {nx}x{spec.params['ny']}-ray map "
-                      f"({sub.n_rays} rays x {spec.n_lens} lenses, {dt:.1f} s)"}
+                      f"({sub.n_rays} rays x {spec.n_lens} lenses, {dt:.1f} s)",
+            "cpu": _cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core_small_map": {"value": c0.interactions / dt0, "unit": "ray·lens/s", "seconds": dt0,
+                                   "sample": "the whole 1024^2-ray, 462-lens map"}}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -181,7 +203,8 @@ def main():
             rs.make_map(spec.params, xy, m, mode="fp32", out=out, workspace=ws32)
         torch.cuda.synchronize()
         result["fp32_mode_value"] = inter * n32 / (time.perf_counter() - t)
-    if not (args.no_batched and args.no_serve and args.no_stats and args.no_farfield and args.no_random):
+    if not (args.no_batched and args.no_serve and args.no_stats and args.no_farfield and args.no_random
+            and args.no_other_maps):
         from paper_1005_5198_amd import bench_extra
         if not args.no_batched:
             result["batched"] = bench_extra.batched(rs, mode=args.mode)
@@ -194,6 +217,9 @@ def main():
             result["far_field"] = bench_extra.far_field(rs)
         if not args.no_random:
             result["random_rays"] = bench_extra.random_rays(rs, mode=args.mode)
+        if not args.no_other_maps:
+            result["config1"] = bench_extra.config1(rs)
+            result["paper_point"] = bench_extra.paper_fig1_point(rs)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -291,3 +291,49 @@ def random_rays(rs, reps: int = 3, mode: str = "mixed") -> dict:
     st = rs.read_stats(ws)
     return {"workload": "config2, random rays", "mode": mode, "ms_per_map": dt * 1e3,
             "interactions_per_s": spec.interactions / dt, "recheck_fraction": st["rays_rechecked"] / spec.n_rays}
+
+
+def _time_map(rs, spec, mode: str, reps: int) -> tuple:
+    xy, m = rs.lens_tensors(spec.lens_xy, spec.lens_m)
+    ws = rs.new_workspace(spec.params, spec.n_lens, mode)
+    out = torch.empty((spec.params["npy"], spec.params["npx"]), dtype=torch.uint32, device="cuda")
+    rs.make_map(spec.params, xy, m, mode=mode, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        rs.make_map(spec.params, xy, m, mode=mode, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    return dt, rs.read_stats(ws), out
+
+
+def single_map(rs, spec, label: str, reps: int = 3, modes=("mixed", "fp32", "farfield")) -> dict:
+    """One workload in each mode: time per map, interactions/s and %FP32 peak (direct modes),
+    the re-check fraction, and whether the far-field map equals the mixed one."""
+    res = {"workload": label, "rays": spec.n_rays, "lenses": spec.n_lens, "interactions": spec.interactions}
+    maps = {}
+    for mode in modes:
+        dt, st, out = _time_map(rs, spec, mode, reps)
+        r = {"ms_per_map": dt * 1e3, "interactions_per_s": spec.interactions / dt,
+             "recheck_fraction": st["rays_rechecked"] / max(spec.n_rays, 1)}
+        if mode != "farfield":
+            r["pct_fp32_peak"] = 10.0 * spec.interactions / dt / 157.3e12
+        res[mode] = r
+        maps[mode] = out
+    if "mixed" in maps and "farfield" in maps:
+        res["farfield_equals_mixed"] = bool(torch.equal(maps["mixed"], maps["farfield"]))
+    return res
+
+
+def config1(rs, reps: int = 3) -> dict:
+    """The 32768^2-ray paper-scale map (462 lenses, 1024^2 px): plain FP32 vs mixed (and far field)."""
+    return single_map(rs, w.config1(), "config1: sigma*=0.4, 462 unit lenses (R=34), 32768^2 rays over 40^2, "
+                                       "1024^2 px source of side 20", reps)
+
+
+def paper_fig1_point(rs, reps: int = 2) -> dict:
+    """The paper's Section 3.1 parameter point sigma=0.4, gamma=0 at 1024^2 px and 2000 rays per
+    pixel (N* = 558 with the paper-rule disc; 5.8e9 rays, 3.25e12 interactions)."""
+    spec = w.paper_point(0.4, 0.0)
+    return single_map(rs, spec, "paper point sigma=0.4 gamma=0: 1024^2 px, 2000 rays/px, paper-rule lens disc",
+                      reps, modes=("mixed", "farfield"))

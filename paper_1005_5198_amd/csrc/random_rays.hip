@@ -84,6 +84,61 @@ __global__ __launch_bounds__(256) void rand_scatter_kernel(const ShootArgs a) {
     }
 }
 
+// FP32 sums over the N lenses of tile entries g .. g+N-1 for RR rays with no
+// shared rows or columns (per ray dx, dy, dy^2, r^2, reciprocal, two FMAs),
+// folded into the FP64 accumulators.
+template <int N, int RR, bool UNIT>
+__device__ __forceinline__ void free_group_sums(const float4 *tile, int g, const float (&rx)[RR],
+                                                const float (&ry)[RR], double (&Ax)[RR], double (&Ay)[RR]) {
+    float sx[RR], sy[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        sx[q] = 0.0f;
+        sy[q] = 0.0f;
+    }
+    if (UNIT) {
+#pragma unroll
+        for (int kk = 0; kk < N; kk += 2) {
+            const float4 l2 = tile[(g + kk) >> 1];
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const float LX = half ? l2.z : l2.x;
+                const float LY = half ? l2.w : l2.y;
+#pragma unroll
+                for (int q = 0; q < RR; ++q) {
+                    const float dx = rx[q] - LX;
+                    const float dy = ry[q] - LY;
+                    const float dy2 = dy * dy;
+                    const float r2 = __builtin_fmaf(dx, dx, dy2);
+                    const float inv = __builtin_amdgcn_rcpf(r2);
+                    sx[q] = __builtin_fmaf(dx, inv, sx[q]);
+                    sy[q] = __builtin_fmaf(dy, inv, sy[q]);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk) {
+            const float4 l = tile[g + kk];
+#pragma unroll
+            for (int q = 0; q < RR; ++q) {
+                const float dx = rx[q] - l.x;
+                const float dy = ry[q] - l.y;
+                const float dy2 = dy * dy;
+                const float r2 = __builtin_fmaf(dx, dx, dy2);
+                const float inv = l.z * __builtin_amdgcn_rcpf(r2);
+                sx[q] = __builtin_fmaf(dx, inv, sx[q]);
+                sy[q] = __builtin_fmaf(dy, inv, sy[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        Ax[q] += (double)sx[q];
+        Ay[q] += (double)sy[q];
+    }
+}
+
 // Up to 64 * WAVES * RR rays of one bin, slots [base, end) of the sorted list;
 // (ox, oy) is the bin centre and [ox +- hx] x [oy +- hy] holds every ray of the bin.
 template <int RR, int WAVES, bool UNIT, int MODE, bool PIX>
@@ -116,60 +171,15 @@ __device__ __forceinline__ void shoot_free_chunk(const ShootArgs &a, uint32_t ba
 
     for (int64_t t0 = 0; t0 < a.n_lens; t0 += LENS_TILE) {
         const int cnt = (int)((a.n_lens - t0) < LENS_TILE ? (a.n_lens - t0) : LENS_TILE);
-        const int cnt_pad = (cnt + GROUP - 1) / GROUP * GROUP;
+        const int cnt_pad = (cnt + GROUP / 2 - 1) / (GROUP / 2) * (GROUP / 2);
         __syncthreads();
         stage_tile<UNIT, MODE, BLOCK_THREADS>(a, t0, cnt, cnt_pad, ox, oy, hx, hy, h, near_r2, k_term, sm, tid, bx,
                                               by);
         __syncthreads();
-        for (int g = 0; g < cnt_pad; g += GROUP) {
-            float sx[RR], sy[RR];
-#pragma unroll
-            for (int q = 0; q < RR; ++q) {
-                sx[q] = 0.0f;
-                sy[q] = 0.0f;
-            }
-            if (UNIT) {
-#pragma unroll
-                for (int kk = 0; kk < GROUP; kk += 2) {
-                    const float4 l2 = tile[(g + kk) >> 1];
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const float LX = half ? l2.z : l2.x;
-                        const float LY = half ? l2.w : l2.y;
-#pragma unroll
-                        for (int q = 0; q < RR; ++q) {
-                            const float dx = rx[q] - LX;
-                            const float dy = ry[q] - LY;
-                            const float dy2 = dy * dy;
-                            const float r2 = __builtin_fmaf(dx, dx, dy2);
-                            const float inv = __builtin_amdgcn_rcpf(r2);
-                            sx[q] = __builtin_fmaf(dx, inv, sx[q]);
-                            sy[q] = __builtin_fmaf(dy, inv, sy[q]);
-                        }
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < GROUP; ++kk) {
-                    const float4 l = tile[g + kk];
-#pragma unroll
-                    for (int q = 0; q < RR; ++q) {
-                        const float dx = rx[q] - l.x;
-                        const float dy = ry[q] - l.y;
-                        const float dy2 = dy * dy;
-                        const float r2 = __builtin_fmaf(dx, dx, dy2);
-                        const float inv = l.z * __builtin_amdgcn_rcpf(r2);
-                        sx[q] = __builtin_fmaf(dx, inv, sx[q]);
-                        sy[q] = __builtin_fmaf(dy, inv, sy[q]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < RR; ++q) {
-                Ax[q] += (double)sx[q];
-                Ay[q] += (double)sy[q];
-            }
-        }
+        // Whole groups in the loop; the last tile may end with half a group, summed after it.
+        const int full = cnt_pad / GROUP * GROUP;
+        for (int g = 0; g < full; g += GROUP) free_group_sums<GROUP, RR, UNIT>(tile, g, rx, ry, Ax, Ay);
+        if (full < cnt_pad) free_group_sums<GROUP / 2, RR, UNIT>(tile, full, rx, ry, Ax, Ay);
     }
 
     double Bx = 0.0, By = 0.0;

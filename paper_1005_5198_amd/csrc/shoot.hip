@@ -28,6 +28,80 @@
 namespace rs {
 namespace {
 
+// FP32 sums over the N lenses of tile entries g .. g+N-1 for this lane's RX x RY
+// rays, folded into the FP64 accumulators: dx per column, dy and dy^2 per row,
+// then per ray r^2, the reciprocal and two FMAs. Every LDS read is a 16-byte
+// broadcast (two lenses of unit mass, or one lens with its mass).
+template <int N, int RX, int RY, bool UNIT>
+__device__ __forceinline__ void group_sums(const float4 *tile, int g, const float (&rxl)[RX], const float (&ryl)[RY],
+                                           double (&Ax)[RY][RX], double (&Ay)[RY][RX]) {
+    float sx[RY][RX], sy[RY][RX];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) {
+            sx[r][c] = 0.0f;
+            sy[r][c] = 0.0f;
+        }
+    if (UNIT) {
+#pragma unroll
+        for (int kk = 0; kk < N; kk += 2) {
+            const float4 q = tile[(g + kk) >> 1];
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const float LX = half ? q.z : q.x;
+                const float LY = half ? q.w : q.y;
+                float dy[RY], dy2[RY], dx[RX];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    dy[r] = ryl[r] - LY;
+                    dy2[r] = dy[r] * dy[r];
+                }
+#pragma unroll
+                for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - LX;
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int c = 0; c < RX; ++c) {
+                        const float r2 = __builtin_fmaf(dx[c], dx[c], dy2[r]);
+                        const float inv = __builtin_amdgcn_rcpf(r2);
+                        sx[r][c] = __builtin_fmaf(dx[c], inv, sx[r][c]);
+                        sy[r][c] = __builtin_fmaf(dy[r], inv, sy[r][c]);
+                    }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk) {
+            const float4 q = tile[g + kk];
+            float dy[RY], dy2[RY], dx[RX];
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                dy[r] = ryl[r] - q.y;
+                dy2[r] = dy[r] * dy[r];
+            }
+#pragma unroll
+            for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - q.x;
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int c = 0; c < RX; ++c) {
+                    const float r2 = __builtin_fmaf(dx[c], dx[c], dy2[r]);
+                    const float inv = q.z * __builtin_amdgcn_rcpf(r2);
+                    sx[r][c] = __builtin_fmaf(dx[c], inv, sx[r][c]);
+                    sy[r][c] = __builtin_fmaf(dy[r], inv, sy[r][c]);
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) {
+            Ax[r][c] += (double)sx[r][c];
+            Ay[r][c] += (double)sy[r][c];
+        }
+}
+
 // One 64 x 32 ray patch. RX x RY rays per lane, WX x WY waves per block; every
 // shape covers the same PATCH_X x PATCH_Y ray patch, so a ray's arithmetic
 // (patch origin, lens offsets, operation order) does not depend on the shape.
@@ -88,79 +162,17 @@ __device__ __forceinline__ void shoot_patch(const ShootArgs &a, int64_t patch, S
 
     for (int64_t t0 = 0; t0 < a.n_lens; t0 += LENS_TILE) {
         const int cnt = (int)((a.n_lens - t0) < LENS_TILE ? (a.n_lens - t0) : LENS_TILE);
-        const int cnt_pad = (cnt + GROUP - 1) / GROUP * GROUP;
+        const int cnt_pad = (cnt + GROUP / 2 - 1) / (GROUP / 2) * (GROUP / 2);
         __syncthreads();  // previous tile fully consumed (and near_count initialised)
         stage_tile<UNIT, MODE, BLOCK_THREADS>(a, t0, cnt, cnt_pad, ox, oy, hx, hy, h, near_r2, k_term, sm, tid, bx,
                                               by);
         __syncthreads();
 
-        for (int g = 0; g < cnt_pad; g += GROUP) {
-            float sx[RY][RX], sy[RY][RX];
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int c = 0; c < RX; ++c) {
-                    sx[r][c] = 0.0f;
-                    sy[r][c] = 0.0f;
-                }
-            if (UNIT) {
-#pragma unroll
-                for (int kk = 0; kk < GROUP; kk += 2) {
-                    const float4 q = tile[(g + kk) >> 1];
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const float LX = half ? q.z : q.x;
-                        const float LY = half ? q.w : q.y;
-                        float dy[RY], dy2[RY], dx[RX];
-#pragma unroll
-                        for (int r = 0; r < RY; ++r) {
-                            dy[r] = ryl[r] - LY;
-                            dy2[r] = dy[r] * dy[r];
-                        }
-#pragma unroll
-                        for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - LX;
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-#pragma unroll
-                            for (int c = 0; c < RX; ++c) {
-                                const float r2 = __builtin_fmaf(dx[c], dx[c], dy2[r]);
-                                const float inv = __builtin_amdgcn_rcpf(r2);
-                                sx[r][c] = __builtin_fmaf(dx[c], inv, sx[r][c]);
-                                sy[r][c] = __builtin_fmaf(dy[r], inv, sy[r][c]);
-                            }
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < GROUP; ++kk) {
-                    const float4 q = tile[g + kk];
-                    float dy[RY], dy2[RY], dx[RX];
-#pragma unroll
-                    for (int r = 0; r < RY; ++r) {
-                        dy[r] = ryl[r] - q.y;
-                        dy2[r] = dy[r] * dy[r];
-                    }
-#pragma unroll
-                    for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - q.x;
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-#pragma unroll
-                        for (int c = 0; c < RX; ++c) {
-                            const float r2 = __builtin_fmaf(dx[c], dx[c], dy2[r]);
-                            const float inv = q.z * __builtin_amdgcn_rcpf(r2);
-                            sx[r][c] = __builtin_fmaf(dx[c], inv, sx[r][c]);
-                            sy[r][c] = __builtin_fmaf(dy[r], inv, sy[r][c]);
-                        }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int c = 0; c < RX; ++c) {
-                    Ax[r][c] += (double)sx[r][c];
-                    Ay[r][c] += (double)sy[r][c];
-                }
-        }
+        // Whole groups in the loop; the last tile may end with half a group, summed
+        // after it (code of its own, so the loop's schedule is that of whole groups).
+        const int full = cnt_pad / GROUP * GROUP;
+        for (int g = 0; g < full; g += GROUP) group_sums<GROUP, RX, RY, UNIT>(tile, g, rxl, ryl, Ax, Ay);
+        if (full < cnt_pad) group_sums<GROUP / 2, RX, RY, UNIT>(tile, full, rxl, ryl, Ax, Ay);
     }
 
     // Block-wide error bound (mixed mode).
@@ -233,7 +245,7 @@ __device__ __forceinline__ void shoot_patch(const ShootArgs &a, int64_t patch, S
 
 // Single map: one block per patch of this launch's rows.
 template <int RX, int RY, int WX, int WY, bool UNIT, int MODE, bool PIX>
-__global__ __launch_bounds__(64 * WX * WY) void shoot_kernel(const ShootArgs a) {
+__global__ __launch_bounds__(64 * WX * WY, (RX * RY <= 8) ? 4 : 1) void shoot_kernel(const ShootArgs a) {
     __shared__ ShootSmem sm;
     shoot_patch<RX, RY, WX, WY, UNIT, MODE, PIX>(a, (int64_t)blockIdx.x, sm, SingleSink{});
 }
