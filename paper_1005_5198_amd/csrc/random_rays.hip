@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void rand_scatter_kernel(const ShootArgs a) {
 
 // FP32 sums over the N lenses of tile entries g .. g+N-1 for RR rays with no
 // shared rows or columns (per ray dx, dy, dy^2, r^2, reciprocal, two FMAs),
-// folded into the FP64 accumulators.
+// folded into the FP64 accumulators. Unit masses: the two lenses of one LDS
+// read share one v_rcp_f32 per ray, of the product of the ray's two r^2 (a
+// ray's arithmetic must not depend on its slot, which the scatter's atomics set).
 template <int N, int RR, bool UNIT>
 __device__ __forceinline__ void free_group_sums(const float4 *tile, int g, const float (&rx)[RR],
                                                 const float (&ry)[RR], double (&Ax)[RR], double (&Ay)[RR]) {
@@ -99,36 +101,37 @@ __device__ __forceinline__ void free_group_sums(const float4 *tile, int g, const
     if (UNIT) {
 #pragma unroll
         for (int kk = 0; kk < N; kk += 2) {
-            const float4 l2 = tile[(g + kk) >> 1];
+            const float4 l2 = tile[(g + kk) >> 1];   // lenses g+kk (x, y) and g+kk+1 (z, w)
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const float LX = half ? l2.z : l2.x;
-                const float LY = half ? l2.w : l2.y;
-#pragma unroll
-                for (int q = 0; q < RR; ++q) {
-                    const float dx = rx[q] - LX;
-                    const float dy = ry[q] - LY;
-                    const float dy2 = dy * dy;
-                    const float r2 = __builtin_fmaf(dx, dx, dy2);
-                    const float inv = __builtin_amdgcn_rcpf(r2);
-                    sx[q] = __builtin_fmaf(dx, inv, sx[q]);
-                    sy[q] = __builtin_fmaf(dy, inv, sy[q]);
-                }
+            for (int q = 0; q < RR; ++q) {
+                const float dxa = rx[q] - l2.x, dya = ry[q] - l2.y;
+                const float dxb = rx[q] - l2.z, dyb = ry[q] - l2.w;
+                const float ra = __builtin_fmaf(dxa, dxa, dya * dya);
+                const float rb = __builtin_fmaf(dxb, dxb, dyb * dyb);
+                const float rab = __builtin_amdgcn_rcpf(ra * rb);
+                const float ia = rb * rab, ib = ra * rab;
+                sx[q] = __builtin_fmaf(dxa, ia, sx[q]);
+                sy[q] = __builtin_fmaf(dya, ia, sy[q]);
+                sx[q] = __builtin_fmaf(dxb, ib, sx[q]);
+                sy[q] = __builtin_fmaf(dyb, ib, sy[q]);
             }
         }
     } else {
 #pragma unroll
-        for (int kk = 0; kk < N; ++kk) {
-            const float4 l = tile[g + kk];
+        for (int kk = 0; kk < N; kk += 2) {
+            const float4 la = tile[g + kk], lb = tile[g + kk + 1];
 #pragma unroll
             for (int q = 0; q < RR; ++q) {
-                const float dx = rx[q] - l.x;
-                const float dy = ry[q] - l.y;
-                const float dy2 = dy * dy;
-                const float r2 = __builtin_fmaf(dx, dx, dy2);
-                const float inv = l.z * __builtin_amdgcn_rcpf(r2);
-                sx[q] = __builtin_fmaf(dx, inv, sx[q]);
-                sy[q] = __builtin_fmaf(dy, inv, sy[q]);
+                const float dxa = rx[q] - la.x, dya = ry[q] - la.y;
+                const float dxb = rx[q] - lb.x, dyb = ry[q] - lb.y;
+                const float ra = __builtin_fmaf(dxa, dxa, dya * dya);
+                const float rb = __builtin_fmaf(dxb, dxb, dyb * dyb);
+                const float rab = __builtin_amdgcn_rcpf(ra * rb);
+                const float ia = la.z * (rb * rab), ib = lb.z * (ra * rab);
+                sx[q] = __builtin_fmaf(dxa, ia, sx[q]);
+                sy[q] = __builtin_fmaf(dya, ia, sy[q]);
+                sx[q] = __builtin_fmaf(dxb, ib, sx[q]);
+                sy[q] = __builtin_fmaf(dyb, ib, sy[q]);
             }
         }
     }
@@ -203,7 +206,8 @@ __device__ __forceinline__ void shoot_free_chunk(const ShootArgs &a, uint32_t ba
             By += sm.red_by[w];
         }
         n_near = sm.near_count;
-        all_flagged = n_near > NEAR_MAX;
+        // (a bin under 1e-6 across could underflow the paired products of r^2)
+        all_flagged = n_near > NEAR_MAX || h < 1.0e-6;
         if (all_flagged) n_near = 0;
     }
 
@@ -223,8 +227,9 @@ __device__ __forceinline__ void shoot_free_chunk(const ShootArgs &a, uint32_t ba
         const double y2 = a.c2 * x2 - Ay[q];
         const double u = (y1 - a.tx0) * a.inv_pixw;
         const double v = (y2 - a.ty0) * a.inv_pixh;
-        int code = classify_ray<MODE>(a, x1, x2, Ax[q], Ay[q], u, v, rx[q], ry[q], Bx, By, n_near, all_flagged,
-                                      sm.near_list, k_term, h_f, tiny_r2);
+        // reciprocals are shared between two lenses of one ray, not between rays
+        int code = classify_ray<MODE>(a, x1, x2, Ax[q], Ay[q], u, v, rx[q], ry[q], rx[q], ry[q], Bx, By, n_near,
+                                      all_flagged, sm.near_list, k_term, h_f, tiny_r2);
         if (!valid) code = INT32_MIN;
 
         n_in += __builtin_popcountll(__ballot(code >= 0));

@@ -15,12 +15,17 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
 // Per-lens FP32 error constants (derivation in the design notes):
 //   |t_hat - t| <= u m (K_TERM |dx| + K_H h) / r^2 for one term t = m dx / r^2,
 //   the FP32 group sum adds u (GROUP - pos) |t_hat| for the lens at position pos.
-// Unit masses: K_TERM covers dx (2.04u), r^2 (6.08u + 4.08u h/r) and rcp (2u, 1 ulp);
-// with masses, the FP32 mass rounding and the extra multiply add 2u more.
-constexpr double K_TERM_UNIT = 10.5;
-constexpr double K_TERM_MASS = 13.0;
+// Unit masses: K_TERM covers dx (2.04u), r^2 (6.08u + 4.08u h/r) and the reciprocal,
+// shared by two terms (two rays of one lens on the grid, two lenses of one ray for
+// random rays): b * rcp(a * b) is within 4u of 1/a (the product, v_rcp_f32's 1 ulp,
+// the final multiply); with masses the FP32 mass rounding and the mass multiply
+// add 2u.
+constexpr double K_TERM_UNIT = 12.5;
+constexpr double K_TERM_MASS = 15.0;
 constexpr double K_GROUP = 1.01;
 constexpr double K_H = 6.5;
+
+constexpr double PAD_OFFSET = 1.0e9;   // exactly representable in FP32
 
 constexpr int OUT = -1;
 constexpr int SINGULAR = -2;
@@ -88,8 +93,11 @@ struct BatchSink {
 };
 
 // Stage lenses t0 .. t0+cnt of the lens array into the LDS tile as FP32 offsets
-// from the block origin (ox, oy), padded to whole groups with far massless
-// lenses. Mixed mode: lenses within 2h of the block's box go to the near list
+// from the block origin (ox, oy), padded to whole half groups with lenses at
+// offset (PAD_OFFSET, 0): massless where masses are stored; with unit masses
+// each adds at most 1/(PAD_OFFSET - hx) to a ray's deflection, which mixed mode
+// adds to the bound (far enough to be negligible, near enough that a product
+// of two r^2 stays finite). Mixed mode: lenses within 2h of the block's box go to the near list
 // (bounded per ray later); the others add their rigorous FP32 error weight for
 // any ray in the box [ox +- hx] x [oy +- hy] to this thread's share (bx, by).
 template <bool UNIT, int MODE, int BLOCK_THREADS>
@@ -98,7 +106,7 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
                                            ShootSmem &sm, int tid, double &bx, double &by) {
     float4 *tile = sm.tile;
         for (int s = tid; s < cnt_pad; s += BLOCK_THREADS) {
-            float fx = 1.0e18f, fy = 0.0f, fm = 0.0f;  // padding lens: far away, massless
+            float fx = (float)PAD_OFFSET, fy = 0.0f, fm = 0.0f;  // padding lens
             if (s < cnt) {
                 const int64_t k = t0 + s;
                 // global-address-space reads (a batch descriptor's pointers are generic)
@@ -114,6 +122,9 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
                     const double ex = fmax(alx - hx, 0.0), ey = fmax(aly - hy, 0.0);
                     const double dmin2 = ex * ex + ey * ey;
                     const int pos = s % GROUP;
+                    // A lens beyond 1e9 could overflow the paired products of r^2: the
+                    // block's rays all go to the FP64 re-check instead.
+                    if (fmax(alx, aly) > 1.0e9) atomicAdd(&sm.near_count, NEAR_MAX + 1);
                     if (dmin2 < near_r2) {
                         const int q = atomicAdd(&sm.near_count, 1);
                         if (q < NEAR_MAX) sm.near_list[q] = NearLens{fx, fy, (float)fabs(m), pos};
@@ -124,6 +135,11 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
                         by += im * (wgt * (aly + hy) + K_H * h);
                     }
                 }
+            } else if (MODE == 1 && UNIT) {
+                // a unit-mass padding lens's whole term, in units of u
+                const double d = PAD_OFFSET - hx;
+                bx += 1.0 / (d * U32);
+                by += hy / (d * d * U32);
             }
             if (UNIT) {
                 float *t2 = reinterpret_cast<float *>(tile);
@@ -138,10 +154,14 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
 // Pixel code of one ray from its FP64 position x, its folded deflection A and
 // its source position (u, v) in pixel units. Mixed mode: the ray's error
 // bound is the block's (Bx, By) plus the near lenses' per-ray terms, and a ray
-// within it of a pixel edge is FLAGGED for the FP64 re-check.
+// within it of a pixel edge is FLAGGED for the FP64 re-check. (rxp, ryp) is the
+// ray whose reciprocals this one's share: a near lens almost on either of the
+// two flags it (their product of r^2 could underflow); a ray with a non-finite
+// position is never counted out, only flagged.
 template <int MODE>
 __device__ __forceinline__ int classify_ray(const ShootArgs &a, double x1, double x2, double Axv, double Ayv, double u,
-                                            double v, float rx, float ry, double Bx, double By, int n_near,
+                                            double v, float rx, float ry, float rxp, float ryp, double Bx,
+                                            double By, int n_near,
                                             bool all_flagged, const NearLens *near_list, double k_term, float h_f,
                                             float tiny_r2) {
     int code;
@@ -157,8 +177,10 @@ __device__ __forceinline__ int classify_ray(const ShootArgs &a, double x1, doubl
             const NearLens nl = near_list[q];
             const float dxn = rx - nl.x, dyn = ry - nl.y;
             const float r2n = dxn * dxn + dyn * dyn;
+            const float dxp = rxp - nl.x, dyp = ryp - nl.y;
+            const float r2p = dxp * dxp + dyp * dyp;
             const float wgt = (float)(k_term + K_GROUP * (double)(GROUP - nl.pos));
-            if (!(r2n > tiny_r2)) {
+            if (!(r2n > tiny_r2) || !(r2p > tiny_r2)) {
                 cx = __builtin_inff();
                 cy = __builtin_inff();
             } else {
@@ -174,11 +196,12 @@ __device__ __forceinline__ int classify_ray(const ShootArgs &a, double x1, doubl
         const double fu = floor(u), fv = floor(v);
         const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Eu) && (fu >= 0.0) && (fu < (double)a.npx);
         const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Ev) && (fv >= 0.0) && (fv < (double)a.npy);
+        const bool fin = isfinite(u) && isfinite(v);
         const bool out_u = (u < -Eu) || (u > (double)a.npx + Eu);
         const bool out_v = (v < -Ev) || (v > (double)a.npy + Ev);
         if (all_flagged) code = FLAGGED;
         else if (ok_u && ok_v) code = (int)((int64_t)fv * a.npx + (int64_t)fu);
-        else if (out_u || out_v) code = OUT;
+        else if (fin && (out_u || out_v)) code = OUT;
         else code = FLAGGED;
     }
     return code;

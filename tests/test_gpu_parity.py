@@ -135,6 +135,26 @@ def test_config2_full_map_sampled(rs):
         assert np.array_equal(pix_m, pix_o)
 
 
+@pytest.mark.parametrize("random_rays", [False, True])
+def test_config1_full_map_staged_equals_exact(rs, random_rays):
+    """The 1.07e9-ray map runs as several launches (8 on the grid, 16 with random rays), each
+    with its own queue and, on the grid, its own super-patch records: the staged re-check gives
+    the same map as the exact sequence for every flagged ray."""
+    s = w.config1()
+    p = dict(s.params)
+    if random_rays:
+        p.update(random_rays=1, seed=13)
+    say("config1 full map, random" if random_rays else "config1 full map, grid")
+    xy, _ = rs.lens_tensors(s.lens_xy)
+    a, st = rs.make_map(p, xy, None, mode="mixed", return_stats=True)
+    b, st_x = rs.make_map(p, xy, None, mode="mixed", return_stats=True, exact_recheck=True)
+    say(f"  re-checked {st['rays_rechecked']}, against every lens {st['rays_rechecked_direct']}")
+    assert torch.equal(a, b)
+    assert st["rays_rechecked"] == st_x["rays_rechecked"] > 10000
+    assert st["rays_rechecked_direct"] < 0.02 * st["rays_rechecked"]
+    assert st["rays_in_map"] + st["rays_out"] + st["rays_singular"] == s.n_rays
+
+
 def test_windows_sum_to_full_map(rs):
     """Ray windows are exact partial maps: their sum equals the full map (checkpoint/resume)."""
     s = w.config0()
