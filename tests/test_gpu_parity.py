@@ -191,6 +191,20 @@ def test_edge_cases(rs, case):
     check_pixels(rs, spec, fp32_budget=2e-3 if case == "single_ray" else 1e-4)
 
 
+def test_shared_reciprocal_range_guards(rs):
+    """The FP32 loop shares one reciprocal between two rows through the product of their r^2.
+    A lens beyond 1e9 (the product could overflow) flags every block, and a patch under 1e-6
+    across (the product could underflow) is flagged whole: both maps still equal the oracle's."""
+    rng = np.random.default_rng(31)
+    lens = np.concatenate([rng.uniform(-9, 9, size=(40, 2)), [[2.0e9, 1.0]]])
+    p = w.make_params(0.3, 0.1, 0.2, (-6.0, -5.0, 12.0, 10.0, 160, 96), (-4.0, -4.0, 8.0, 8.0, 40, 40))
+    st = check_mixed_exact(rs, w.MapSpec("far_lens", p, lens, None))
+    assert st["rays_rechecked"] == 160 * 96
+    tiny = w.make_params(0.3, 0.0, 0.1, (0.25, 0.5, 2e-8, 1e-8, 128, 64), (-100.0, -100.0, 200.0, 200.0, 64, 64))
+    st = check_mixed_exact(rs, w.MapSpec("tiny_patch", tiny, rng.uniform(-3, 3, size=(25, 2)), None))
+    assert st["rays_rechecked"] == 128 * 64 and st["rays_in_map"] > 0
+
+
 def test_empty_window(rs):
     s = w.config0().window(10, 10, 0, 1024)
     m_g, st = gpu_map(rs, s, "mixed")
