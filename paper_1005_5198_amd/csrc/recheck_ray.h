@@ -111,16 +111,30 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
     double x1, x2;
     ray_xy(a, i, j, x1, x2);
     double a1 = 0.0, a2 = 0.0;
+    // This lane's lens of the next chunk is loaded one chunk ahead, so the memory
+    // latency overlaps the current chunk's division and sequential sum.
+    double LX = 0.0, LY = 0.0, LM = 1.0;
+    if (lane < a.n_lens) {
+        LX = lens_x(a, lane);
+        LY = lens_y(a, lane);
+        if (!UNIT) LM = lens_mass(a, lane);
+    }
     for (int64_t k0 = 0; k0 < a.n_lens; k0 += 64) {
         const int64_t k = k0 + lane;
+        const double X = LX, Y = LY, M = LM;
+        if (k + 64 < a.n_lens) {
+            LX = lens_x(a, k + 64);
+            LY = lens_y(a, k + 64);
+            if (!UNIT) LM = lens_mass(a, k + 64);
+        }
         double t1 = 0.0, t2 = 0.0;
         bool zero = false;
         if (k < a.n_lens) {
-            const double d1 = x1 - lens_x(a, k);
-            const double d2 = x2 - lens_y(a, k);
+            const double d1 = x1 - X;
+            const double d2 = x2 - Y;
             const double r2 = d1 * d1 + d2 * d2;
             zero = (r2 == 0.0);
-            const double m = UNIT ? 1.0 : lens_mass(a, k);
+            const double m = UNIT ? 1.0 : M;
             const double f = m / r2;
             t1 = f * d1;
             t2 = f * d2;
