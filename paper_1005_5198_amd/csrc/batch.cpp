@@ -147,8 +147,9 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
     void *tok = nullptr;
     profile_begin(s, &tok);
     e = launch_shoot_batch(b, shape, 0, s);
-    if (e != hipSuccess) return hip_fail(e, "batched deflection kernel");
+    // profile_end takes the event in every case, also after a failed launch
     int rc = profile_end(s, tok, interactions);
+    if (e != hipSuccess) return hip_fail(e, "batched deflection kernel");
     if (rc) return rc;
     if (mode == RS_MIXED) {
         e = launch_batch_super(b, s);

@@ -180,15 +180,51 @@ void profile_begin(hipStream_t stream, void **token) {
     *token = a;
 }
 
+// Takes ownership of token (the event profile_begin recorded), also on failure.
 int profile_end(hipStream_t stream, void *token, double interactions) {
     if (!token) return RS_OK;
     hipEvent_t a = static_cast<hipEvent_t>(token), b = nullptr;
-    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, stream) != hipSuccess)
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(RS_EHIP, "hipEventCreate failed");
+    }
+    if (hipEventRecord(b, stream) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
         return fail(RS_EHIP, "hipEventRecord failed");
+    }
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.pending.push_back({a, b, interactions});
     return RS_OK;
 }
+
+// A profile_begin event that an early return would otherwise leak.
+struct ProfileToken {
+    void *tok = nullptr;
+    ProfileToken() = default;
+    ProfileToken(const ProfileToken &) = delete;
+    ProfileToken &operator=(const ProfileToken &) = delete;
+    ~ProfileToken() {
+        if (tok) (void)hipEventDestroy(static_cast<hipEvent_t>(tok));
+    }
+    void *release() {
+        void *t = tok;
+        tok = nullptr;
+        return t;
+    }
+};
+
+// The deflection launches' timing events, destroyed on every return.
+struct EventPair {
+    hipEvent_t first = nullptr, last = nullptr;
+    EventPair() = default;
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    ~EventPair() {
+        if (first) (void)hipEventDestroy(first);
+        if (last) (void)hipEventDestroy(last);
+    }
+};
 
 int choose_shape(int mode, bool unit, int64_t n_lens);
 
@@ -296,10 +332,10 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         }
     }
     if (shape < 0 && !pl.random && p->mode != RS_FARFIELD) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
-    hipEvent_t t_first = nullptr, t_last = nullptr;
+    EventPair ev;
     if (kernel_ms) {
         *kernel_ms = 0.0f;
-        if (hipEventCreate(&t_first) != hipSuccess || hipEventCreate(&t_last) != hipSuccess)
+        if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.last) != hipSuccess)
             return fail(RS_EHIP, "hipEventCreate failed");
     }
     float timed_ms = 0.0f;
@@ -311,9 +347,9 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
             a.ff_i0 = a.i0;
             a.ff_j0 = a.jc0;
         }
-        void *tok = nullptr;
-        profile_begin(stream, &tok);
-        if (kernel_ms && hipEventRecord(t_first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
+        ProfileToken tok;
+        profile_begin(stream, &tok.tok);
+        if (kernel_ms && hipEventRecord(ev.first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
         if (pl.random) {
             random_bins((a.jc1 - a.jc0) * pl.W, p->sw, p->sh, a.nbx_r, a.nby_r);
             a.bw = p->sw / (double)a.nbx_r;
@@ -329,12 +365,12 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
         if (e != hipSuccess) return hip_fail(e, "deflection kernel");
         if (kernel_ms) {
             float ms = 0.0f;
-            if (hipEventRecord(t_last, stream) != hipSuccess || hipEventSynchronize(t_last) != hipSuccess ||
-                hipEventElapsedTime(&ms, t_first, t_last) != hipSuccess)
+            if (hipEventRecord(ev.last, stream) != hipSuccess || hipEventSynchronize(ev.last) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev.first, ev.last) != hipSuccess)
                 return fail(RS_EHIP, "timing the deflection kernel failed");
             timed_ms += ms;
         }
-        rc = profile_end(stream, tok, (double)(a.jc1 - a.jc0) * (double)pl.W * (double)n_lens);
+        rc = profile_end(stream, tok.release(), (double)(a.jc1 - a.jc0) * (double)pl.W * (double)n_lens);
         if (rc) return rc;
         if (p->mode != RS_FP32) {
             r.jc0 = a.jc0;
@@ -353,8 +389,6 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
     }
     if (kernel_ms) {
         *kernel_ms = timed_ms;
-        (void)hipEventDestroy(t_first);
-        (void)hipEventDestroy(t_last);
         if (hipStreamSynchronize(stream) != hipSuccess) return fail(RS_EHIP, "hipStreamSynchronize failed");
     }
     return RS_OK;

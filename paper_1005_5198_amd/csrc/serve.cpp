@@ -384,6 +384,9 @@ int rs_server_create(const rs_server_cfg *cfg, rs_server **out) {
         hipStreamCreateWithFlags(&s->admit, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->admitted_ev, hipEventDisableTiming) != hipSuccess) {
+        for (hipStream_t st : {s->step_stream[0], s->step_stream[1], s->admit, s->copy})
+            if (st) (void)hipStreamDestroy(st);
+        if (s->admitted_ev) (void)hipEventDestroy(s->admitted_ev);
         (void)hipFree(s->pool);
         delete s;
         return fail(RS_EHIP, "cannot create streams");
