@@ -10,7 +10,8 @@ namespace {
 // of the shooting rectangle, the bins' offsets are scanned, and the rays are
 // scattered into bin order (index and FP64 position); then one block deflects
 // the rays of one bin, relative to the bin's centre, with the same lens tiles,
-// FP32 sum, FP64 folding, error bound and binning as a grid patch. A ray's
+// FP32 sum, FP64 folding, error bound and binning as a grid patch (the shared
+// reciprocal pairs two lenses of a ray rather than two rays). A ray's
 // arithmetic depends only on its position and its bin, not on its slot.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t bin_of(const ShootArgs &a, double x1, double x2) {

@@ -1,19 +1,23 @@
 // FP64 re-evaluation of rays whose FP32 source position is within its error
 // bound of a pixel edge (the arithmetic lives in recheck_ray.h).
 //
-// Two stages keep the exact evaluation rare:
-//   stage A (fast_ray): FP64 with fused multiply-adds and a bound that also
-//     covers the definition's own FP64 rounding; it decides almost every
-//     queued ray identically to the definition and marks the rest;
+// Three stages keep the work per queued ray small and the exact evaluation rare:
+//   stage F (far_ray.h, farfield.hip): the ray's super-patch FP64 expansion
+//     plus the lenses listed near the super-patch, under a rigorous bound; it
+//     places all but a few queued rays;
+//   stage A (fast_ray): FP64 over every lens with fused multiply-adds and a
+//     bound that also covers the definition's own FP64 rounding; it decides
+//     almost every ray stage F left, identically to the definition, and marks
+//     the rest;
 //   stage B (exact_ray_wave): the marked rays, one wave per ray, with the
 //     definition's exact operation sequence.
 // RS_EXACT_RECHECK runs the exact sequence for every queued ray instead (one
 // thread per ray).
 //
-// Single map: the queue holds uint32 chunk-relative ray indices. On the
-// regular grid the far-field stage (farfield.hip) runs first and marks the
-// entries it decided RESOLVED; stage A skips them and picks its form from the
-// number left (*qlive).
+// Single map: the queue holds uint32 chunk-relative ray indices. Unless the
+// caller asked for the exact sequence only, the far-field stage (farfield.hip)
+// runs first and marks the entries it decided RESOLVED; stage A skips them and
+// picks its form from the number left (*qlive).
 // Batch: the deflection kernel sets one bit per flagged ray in each map's
 // bitmap; a persistent scan compacts the set bits per wave and the map's
 // descriptor supplies its parameters and its super-patch records (stage F).

@@ -10,17 +10,18 @@
 //    of LENS_TILE, converted once per block from FP64 to FP32 offsets relative
 //    to the patch centre, so FP32 carries small numbers and the per-block
 //    conversion is paid once per lens per 2048 rays.
-//  * Each lane owns RX x RY rays (4x2, 4x4, 8x2 or 8x4: a tuned choice); per
-//    lens it computes dx for RX columns and dy, dy^2 for RY rows, then
-//    r^2 = fma(dx, dx, dy^2), v_rcp_f32, and two FMAs per ray. Every LDS read
-//    is a 16-byte broadcast of two lenses.
+//  * Each lane owns RX x RY rays (4x2, 4x4, 8x2 or 8x4: a tuned choice), its
+//    rows in adjacent pairs; per lens it computes dx for RX columns and dy,
+//    dy^2 for RY rows, then r^2 = fma(dx, dx, dy^2) per ray, one v_rcp_f32 per
+//    pair of rows (of the product of their r^2) and three multiplies, and two
+//    FMAs per ray. Every LDS read is a 16-byte broadcast of two lenses.
 //  * The sum runs in FP32 over GROUP lenses, then each partial is folded
 //    exactly into an FP64 accumulator, so FP32 rounding never sees the large
 //    running total.
 //  * Mixed mode: while staging lenses the block also sums a rigorous bound on
 //    the FP32 error of every ray in the patch (lenses close to the patch are
 //    bounded per ray instead). A ray whose bound reaches a pixel edge goes to a
-//    queue that an FP64 kernel re-evaluates with the plain definition.
+//    queue that the FP64 re-check stages decide exactly as the definition does.
 //  * Binning uses wave-aggregated atomics: lanes that hit the same pixel add
 //    their count with one atomic.
 #include "shoot_common.h"
