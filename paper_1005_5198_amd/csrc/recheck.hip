@@ -15,8 +15,8 @@
 // thread per ray).
 //
 // Single map: the queue holds uint32 chunk-relative ray indices. Unless the
-// caller asked for the exact sequence only, the far-field stage (farfield.hip)
-// runs first and marks the entries it decided RESOLVED; stage A skips them and
+// caller asked for the exact sequence only (or a random-ray window holds few of
+// its map's rays), the far-field stage (farfield.hip) runs first and marks the entries it decided RESOLVED; stage A skips them and
 // picks its form from the number left (*qlive).
 // Batch: the deflection kernel sets one bit per flagged ray in each map's
 // bitmap; a persistent scan compacts the set bits per wave and the map's
