@@ -127,15 +127,19 @@ const char *rs_last_error(void);
 
 /*
  * Workspace bytes rs_make_map / rs_ray_pixels need for these parameters and
- * lens count (stats counters plus, for RS_MIXED, the FP64 re-check queue).
+ * lens count: the stats counters; for RS_MIXED and RS_FARFIELD the FP64
+ * re-check queue (4 bytes per ray of the largest launch, up to 2^27 rays) and
+ * the super-patch records of the far-field expansion or re-check stage (about
+ * 16.7 KB per 32768 rays); for random rays the bin arrays and the sorted ray
+ * list (20 bytes per ray of the largest launch, up to 2^26 rays).
  * Returns 0 if the parameters are invalid.
  */
 size_t rs_workspace_bytes(const rs_map_params *params, int64_t n_lens);
 
 /*
  * Build the count map of the ray window (Section 2, Eq. (sigma) and Eq. (mu_ij)).
- *   lens_xy  device, float64 [n_lens][2] (x, y) positions, 16-byte aligned
- *   lens_m   device, float64 [n_lens] masses, or NULL for unit masses
+ *   lens_xy  device, float64 [n_lens][2] (x, y) positions, 8-byte aligned
+ *   lens_m   device, float64 [n_lens] masses (8-byte aligned), or NULL for unit masses
  *   n_lens   >= 0
  *   map      device, uint32 [npy][npx]; zeroed first unless RS_ACCUMULATE
  *   workspace / workspace_bytes  device scratch of at least rs_workspace_bytes()
@@ -231,9 +235,10 @@ typedef struct {
 } rs_map_request;
 
 /*
- * Workspace bytes for this batch: descriptors, counters, and two bits per ray
- * (rays to re-check, rays left to the exact stage). Returns 0 if a request is
- * invalid.
+ * Workspace bytes for this batch: descriptors, counters, two bits per ray
+ * (rays to re-check, rays left to the exact stage) and, in RS_MIXED, each
+ * map's super-patch records for the far-field re-check stage (about 4.4 KB per
+ * 32768 rays). Returns 0 if a request is invalid.
  */
 size_t rs_batch_workspace_bytes(const rs_map_request *requests, int32_t n);
 
@@ -291,7 +296,8 @@ typedef struct {
 
 typedef struct rs_server rs_server;
 
-/* Start a server on the current device: allocates its pool and two streams, starts its thread. */
+/* Start a server on the current device: allocates its pool and four streams (two for launch
+   steps, one for admission, one for copies back), starts its thread. */
 int rs_server_create(const rs_server_cfg *cfg, rs_server **server);
 
 /*
