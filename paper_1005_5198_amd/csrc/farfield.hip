@@ -66,6 +66,32 @@ struct FarAcc {
         sdef += am * 1.4142135623730951 / (ad - h);
         nfar += 1.0;
     }
+    // Sum of one wave's lanes (butterfly) into out[FAR_REC] (shared), written by lane 0.
+    __device__ void reduce_wave(double *out) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int n = 0; n < FAR_P; ++n) {
+                c1[n] += __shfl_xor(c1[n], off);
+                c2[n] += __shfl_xor(c2[n], off);
+            }
+            sfar += __shfl_xor(sfar, off);
+            trunc += __shfl_xor(trunc, off);
+            sdef += __shfl_xor(sdef, off);
+            nfar += __shfl_xor(nfar, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int n = 0; n < FAR_P; ++n) {
+                out[n] = c1[n];
+                out[FAR_P + n] = c2[n];
+            }
+            out[2 * FAR_P] = sfar;
+            out[2 * FAR_P + 1] = trunc;
+            out[2 * FAR_P + 2] = sdef;
+            out[2 * FAR_P + 3] = nfar;
+        }
+    }
     // Block sum into out[FAR_REC] (shared); lanes by butterfly, then waves in index order.
     __device__ void reduce(double (*part)[FAR_REC], double *out) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -176,6 +202,27 @@ struct FarSmem {
     double tc[2 * FAR_P];        // total coefficients about z0
 };
 
+// One lens of the super-patch's list, seen from patch centre (ox, oy): far
+// from the patch -> its expansion (acc); else the LDS near list.
+template <bool UNIT>
+__device__ __forceinline__ void patch_candidate(const ShootArgs &a, int64_t k, double ox, double oy, double h,
+                                                double near_r2, FarAcc &acc, FarSmem &sm) {
+    const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
+    const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
+    const double d1 = ox - X, d2 = oy - Y;
+    const double r2 = d1 * d1 + d2 * d2;
+    if (!(r2 >= near_r2)) {
+        const int j = atomicAdd(&sm.near_count, 1);
+        if (j < NEAR_EXP) {
+            sm.near_x[j] = X;
+            sm.near_y[j] = Y;
+            sm.near_m[j] = m;
+        }
+        return;
+    }
+    acc.add(d1, d2, r2, m, h);
+}
+
 // Level 2: one block per patch.
 template <bool UNIT, bool PIX>
 __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArgs a) {
@@ -208,29 +255,23 @@ __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArg
     // The super-patch's nearer lenses: far from this patch -> its own expansion; else direct.
     FarAcc acc;
     acc.zero();
-    const int64_t n_cand = scan_all ? a.n_lens : (int64_t)listed;
-    for (int64_t q = tid; q < n_cand; q += FAR_THREADS) {
-        const int64_t k = scan_all ? q : (int64_t)list[1 + q];
-        const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
-        if (scan_all) {   // the same test the super kernel made
-            const double e1 = cx - X, e2 = cy - Y;
-            if (e1 * e1 + e2 * e2 >= super_r2) continue;
+    if (!scan_all) {
+        // The list (a few dozen lenses) by wave 0 alone, reduced over its 64 lanes:
+        // a block-wide reduction of the 36 sums costs more than the lenses.
+        if (tid < 64) {
+            for (int64_t q = lane; q < (int64_t)listed; q += 64)
+                patch_candidate<UNIT>(a, (int64_t)list[1 + q], ox, oy, h, near_r2, acc, sm);
+            acc.reduce_wave(sm.pc);
         }
-        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
-        const double d1 = ox - X, d2 = oy - Y;
-        const double r2 = d1 * d1 + d2 * d2;
-        if (!(r2 >= near_r2)) {
-            const int j = atomicAdd(&sm.near_count, 1);
-            if (j < NEAR_EXP) {
-                sm.near_x[j] = X;
-                sm.near_y[j] = Y;
-                sm.near_m[j] = m;
-            }
-            continue;
+        __syncthreads();
+    } else {
+        for (int64_t q = tid; q < a.n_lens; q += FAR_THREADS) {
+            const double e1 = cx - a.lens_xy[2 * q], e2 = cy - a.lens_xy[2 * q + 1];
+            if (e1 * e1 + e2 * e2 >= super_r2) continue;   // the same test the super kernel made
+            patch_candidate<UNIT>(a, q, ox, oy, h, near_r2, acc, sm);
         }
-        acc.add(d1, d2, r2, m, h);
+        acc.reduce(sm.part, sm.pc);
     }
-    acc.reduce(sm.part, sm.pc);
 
     // Re-centre the super expansion: sum_n C_n (e + v)^n = sum_m v^m sum_{n>=m} binom(n,m) e^(n-m) C_n,
     // v = -w = z0 - z, e = zS - z0; then add this patch's own coefficients.
