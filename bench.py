@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-farfield", action="store_true", help="skip the far-field expansion mode timing")
     ap.add_argument("--no-tune", action="store_true", help="keep the default thread shape (skip the autotuner)")
     ap.add_argument("--no-random", action="store_true", help="skip the random-ray map timing")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the plain-FP32 mode's changed-ray fraction and map error on the config-2 map")
     ap.add_argument("--no-other-maps", action="store_true",
                     help="skip the 32768^2-ray map and the paper's sigma=0.4 point (each mode)")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -204,7 +206,7 @@ def main():
         torch.cuda.synchronize()
         result["fp32_mode_value"] = inter * n32 / (time.perf_counter() - t)
     if not (args.no_batched and args.no_serve and args.no_stats and args.no_farfield and args.no_random
-            and args.no_other_maps):
+            and args.no_other_maps and args.no_accuracy):
         from paper_1005_5198_amd import bench_extra
         if not args.no_batched:
             result["batched"] = bench_extra.batched(rs, mode=args.mode)
@@ -217,6 +219,8 @@ def main():
             result["far_field"] = bench_extra.far_field(rs)
         if not args.no_random:
             result["random_rays"] = bench_extra.random_rays(rs, mode=args.mode)
+        if not args.no_accuracy:
+            result["fp32_accuracy"] = bench_extra.fp32_accuracy(rs)
         if not args.no_other_maps:
             result["config1"] = bench_extra.config1(rs)
             result["paper_point"] = bench_extra.paper_fig1_point(rs)

@@ -3,6 +3,8 @@
 batched(): the 64-map batch (config 3 distribution) in one persistent launch
 sequence vs the same maps one at a time through rs_make_map; every batched map
 is compared with its one-at-a-time result (bit-identical).
+The other legs: the request loop (served), map statistics, the far-field mode,
+random rays, the plain-FP32 mode's accuracy, and two more single-map workloads.
 """
 from __future__ import annotations
 
@@ -291,6 +293,26 @@ def random_rays(rs, reps: int = 3, mode: str = "mixed") -> dict:
     st = rs.read_stats(ws)
     return {"workload": "config2, random rays", "mode": mode, "ms_per_map": dt * 1e3,
             "interactions_per_s": spec.interactions / dt, "recheck_fraction": st["rays_rechecked"] / spec.n_rays}
+
+
+def fp32_accuracy(rs) -> dict:
+    """Plain-FP32 mode against the definition on the config-2 map (19200 x 3840 rays, 17240
+    lenses): the fraction of rays whose pixel changes, from the per-ray pixel indices of both
+    modes (the mixed mode's equal the definition's ray for ray), and the relative L1 error
+    sum|fp32 - exact| / sum(exact) of the count map."""
+    spec = w.config2()
+    xy, _ = rs.lens_tensors(spec.lens_xy)
+    pix_m = rs.ray_pixels(spec.params, xy, None, mode="mixed")
+    pix_f = rs.ray_pixels(spec.params, xy, None, mode="fp32")
+    changed = int((pix_m != pix_f).sum().item())
+    del pix_m, pix_f
+    map_m = rs.make_map(spec.params, xy, None, mode="mixed").to(torch.int64)
+    map_f = rs.make_map(spec.params, xy, None, mode="fp32").to(torch.int64)
+    l1 = int((map_f - map_m).abs().sum().item())
+    total = int(map_m.sum().item())
+    return {"workload": "config2", "rays": spec.n_rays, "rays_changed_pixel": changed,
+            "changed_fraction": changed / spec.n_rays, "budget": 1e-4,
+            "map_relative_l1": l1 / max(total, 1)}
 
 
 def _time_map(rs, spec, mode: str, reps: int) -> tuple:
