@@ -318,11 +318,30 @@ def pin_random_mean_mu(orc):
     assert st["rays_in_map"] + st["rays_out"] == n
 
 
+def pin_random_vs_grid_lensed(orc, lens_seed=31, ray_seed=13):
+    """Lensed map: random ray positions give each pixel its regular-grid count only as a mean,
+    with Poisson (multinomial) scatter (Section 3.1), so the standardised residuals
+    (random - grid)/sqrt(grid) over well-filled pixels have mean ~0 and variance ~1 (a little
+    above 1: the grid's own quadrature error adds to the scatter)."""
+    rng = np.random.default_rng(lens_seed)
+    lens = rng.uniform(-3.0, 3.0, size=(6, 2))
+    shoot, src = (-8.0, -8.0, 16.0, 16.0, 640, 640), (-4.0, -4.0, 8.0, 8.0, 40, 40)
+    grid, _ = orc.make_map(_p(0.0, 0.0, shoot, src), lens)
+    rnd, _ = orc.make_map(_random(_p(0.0, 0.0, shoot, src), ray_seed), lens)
+    g = grid.astype(np.float64)
+    sel = g >= 50.0
+    z = (rnd.astype(np.float64)[sel] - g[sel]) / np.sqrt(g[sel])
+    assert sel.sum() > 1000
+    assert abs(z.mean()) < 4.0 / math.sqrt(sel.sum()), f"random-ray mean off the grid map: {z.mean():.3f}"
+    assert 0.85 < z.var() < 1.25, f"random-ray scatter not Poisson: variance {z.var():.3f}"
+
+
 ALL_PINS = {
     "philox": pin_philox,
     "random_identity": pin_random_identity,
     "random_wiring": pin_random_wiring,
     "random_mean_mu": pin_random_mean_mu,
+    "random_vs_grid_lensed": pin_random_vs_grid_lensed,
     "identity": pin_identity,
     "separable": pin_separable,
     "mean_mu": pin_mean_mu,
