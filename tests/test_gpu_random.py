@@ -83,6 +83,27 @@ def test_random_identity_matches_oracle_and_scatters(rs):
     assert 70.0 < var < 130.0
 
 
+def test_random_scatters_around_grid_map(rs):
+    """The config-0 lens field on a 64^2-px source grid (64 rays per pixel unlensed): the
+    random-ray map equals the oracle's, and against the regular-grid map its counts scatter as
+    Poisson draws around the same mean (Section 3.1): standardised residuals over well-filled
+    pixels have mean ~0 and variance ~1."""
+    s = w.config0()
+    p = dict(s.params)
+    p.update(npx=64, npy=64)
+    grid = rs.make_map(p, s.lens_xy, mode="mixed").cpu().numpy()
+    spec = randomized(w.MapSpec("c0_64px", p, s.lens_xy, None), 5)
+    check_exact(rs, spec)
+    rnd = rs.make_map(spec.params, s.lens_xy, mode="mixed").cpu().numpy()
+    g = grid.astype(np.float64)
+    sel = g >= 50.0
+    z = (rnd.astype(np.float64)[sel] - g[sel]) / np.sqrt(g[sel])
+    say(f"  residuals over {int(sel.sum())} pixels: mean {z.mean():.4f}, variance {z.var():.3f}")
+    assert sel.sum() > 2000
+    assert abs(z.mean()) < 4.0 / np.sqrt(sel.sum())
+    assert 0.85 < z.var() < 1.25
+
+
 def test_random_config2_windows(rs):
     s = randomized(w.config2(), 11)
     for (i0, i1, j0, j1) in ((9000, 10000, 1800, 1864), (0, 64, 0, 3840), (19199, 19200, 3839, 3840)):
