@@ -70,7 +70,9 @@ int validate(const rs_map_params *p, int64_t n_lens) {
     if (!p) return fail(RS_EINVAL, "params is NULL");
     if (p->nx <= 0 || p->ny <= 0) return fail(RS_EINVAL, "ray grid must be positive (nx=%lld ny=%lld)", (long long)p->nx, (long long)p->ny);
     if (p->npx <= 0 || p->npy <= 0) return fail(RS_EINVAL, "source grid must be positive");
-    if (p->npx * p->npy >= (int64_t(1) << 31)) return fail(RS_EINVAL, "source map must have fewer than 2^31 pixels");
+    // each side below 2^31 first, so that the product cannot overflow
+    if (p->npx >= (int64_t(1) << 31) || p->npy >= (int64_t(1) << 31) || p->npx * p->npy >= (int64_t(1) << 31))
+        return fail(RS_EINVAL, "source map must have fewer than 2^31 pixels");
     if (!finite_pos(p->sw) || !finite_pos(p->sh)) return fail(RS_EINVAL, "shooting extents must be finite and > 0");
     if (!finite_pos(p->tw) || !finite_pos(p->th)) return fail(RS_EINVAL, "source extents must be finite and > 0");
     if (!std::isfinite(p->sx0) || !std::isfinite(p->sy0) || !std::isfinite(p->tx0) || !std::isfinite(p->ty0))

@@ -74,6 +74,17 @@ def test_make_map_rejects_before_device_work(lib, field, value):
     assert lib.rs_last_error()
 
 
+@pytest.mark.parametrize("npx,npy", [(1 << 31, 1), (1 << 16, 1 << 15), (1 << 32, 1 << 32)])
+def test_make_map_rejects_huge_source_grids(lib, npx, npy):
+    """2^31 pixels or more is refused, also where npx * npy would wrap around in 64 bits."""
+    from paper_1005_5198_amd import api, _lib, workloads as w
+    c = api.to_params(w.config0().params)
+    c.npx, c.npy = npx, npy
+    rc = lib.rs_make_map(ctypes.byref(c), None, None, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
+    assert rc == _lib.RS_EINVAL
+    assert b"2^31 pixels" in lib.rs_last_error()
+
+
 def test_make_map_rejects_null_outputs(lib):
     from paper_1005_5198_amd import api, _lib, workloads as w
     s = w.config0()
