@@ -304,7 +304,8 @@ int rs_server_create(const rs_server_cfg *cfg, rs_server **server);
  * Queue one map. The parameters and the HOST lens arrays are copied before the
  * call returns; map_host (HOST, uint32 [npy][npx], or NULL to discard) must stay
  * valid until rs_server_wait returns for the ticket. The window must hold fewer
- * than 2^32 rays. Errors: RS_EINVAL, RS_ECANCELED (server stopping).
+ * than 2^32 rays. Errors: RS_EINVAL, RS_ECANCELED (server stopping), RS_EHIP
+ * (the server has stopped after a device error or found no device).
  */
 int rs_server_submit(rs_server *server, const rs_map_params *params, const double *lens_xy_host,
                      const double *lens_m_host, int64_t n_lens, uint32_t *map_host, uint64_t *ticket);
@@ -315,7 +316,8 @@ int rs_server_poll(rs_server *server, uint64_t ticket, int *done);
 /*
  * Block until the request has finished, then release the ticket. Returns
  * RS_OK (map written, stats and latency filled), RS_ECANCELED, RS_ENOMEM (its
- * footprint exceeds the whole pool) or RS_EHIP.
+ * footprint exceeds the whole pool) or RS_EHIP (a device error: the server then
+ * fails every unfinished request and refuses new ones).
  */
 int rs_server_wait(rs_server *server, uint64_t ticket, rs_map_stats *stats, double *latency_s);
 

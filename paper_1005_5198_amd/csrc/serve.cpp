@@ -94,7 +94,7 @@ struct rs_server {
     std::map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
     bool stop = false;
-    bool dead = false;   // the scheduler thread could not start
+    bool dead = false;   // the scheduler thread stopped (no device, or a device error)
     std::thread thread;
 
     std::deque<Step> inflight;
@@ -115,7 +115,22 @@ struct rs_server {
     bool launch_step();
     void retire_step(Step &s);
     void finish(Request &r, int state, int error);
+    void fail_all(int error);
 };
+
+// The scheduler thread cannot go on (no device, or a device error): every request
+// not yet finished fails with error, the steps in flight are dropped, and the
+// server refuses new submissions. Called with mu held.
+void rs_server::fail_all(int error) {
+    dead = true;
+    for (Step &st : inflight) {
+        if (st.ev_start) (void)hipEventDestroy(st.ev_start);
+        if (st.ev_end) (void)hipEventDestroy(st.ev_end);
+    }
+    inflight.clear();
+    for (auto &kv : reqs)
+        if (kv.second.state < DONE) finish(kv.second, FAILED, error);
+}
 
 void rs_server::finish(Request &r, int state, int error) {
     if (r.has_lens) arena.release(r.off_lens);
@@ -275,9 +290,7 @@ void rs_server::run() {
     std::unique_lock<std::mutex> lk(mu);
     if (hipSetDevice(device) != hipSuccess) {
         // no device for this thread: nothing can run, so fail everything now and later
-        dead = true;
-        for (auto &kv : reqs)
-            if (kv.second.state < DONE) finish(kv.second, FAILED, RS_EHIP);
+        fail_all(RS_EHIP);
         return;
     }
     for (;;) {
@@ -358,6 +371,11 @@ void rs_server::run() {
                 Step done = std::move(inflight.front());
                 inflight.pop_front();
                 retire_step(done);
+            } else if (q != hipErrorNotReady) {
+                // the device reported an error: nothing more can run, so fail every
+                // unfinished request and stop (submissions are refused from now on)
+                fail_all(RS_EHIP);
+                return;
             }
             continue;
         }
@@ -422,7 +440,7 @@ int rs_server_submit(rs_server *s, const rs_map_params *params, const double *le
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return fail(RS_ECANCELED, "server is stopping");
-        if (s->dead) return fail(RS_EHIP, "server thread has no device");
+        if (s->dead) return fail(RS_EHIP, "server stopped: no device or a device error");
         r.ticket = j.ticket = s->next_ticket++;
         if (s->t_first_submit < 0) s->t_first_submit = r.t_submit;
         s->reqs.emplace(r.ticket, std::move(r));
