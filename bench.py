@@ -187,6 +187,10 @@ def main():
         "pct_fp32_peak": FLOP_PER_INTERACTION * value / (FP32_PEAK_TFLOPS * 1e12),
         "maps_per_s": args.steps / elapsed,
         "recheck_fraction": stats["rays_rechecked"] / spec.n_rays,
+        # wall time per map outside the deflection launches: map fill, super-patch records,
+        # the FP64 re-check stages and launch gaps, and its share of the step
+        "non_deflection_ms_per_map": ms_per_step - kernel_ms / args.steps,
+        "non_deflection_share": (ms_per_step - kernel_ms / args.steps) / ms_per_step,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_PEAK_TFLOPS,
                      "traffic": TRAFFIC_BYTES_PER_LAUNCH,
