@@ -76,6 +76,28 @@ def new_workspace(params: dict, n_lens: int, mode: str = "mixed", device=None) -
     return torch.empty(workspace_bytes(params, n_lens, mode), dtype=torch.uint8, device=device or _device())
 
 
+def map_params(sigma_star: float, sigma_c: float, gamma: float, shoot, src, window=None) -> dict:
+    """The parameter dict of one map: the macro model (Section 2, Eq. (sigma)), the shooting grid
+    shoot = (x0, y0, w, h, nx, ny) of cell-centred rays, the source grid src = (x0, y0, w, h,
+    npx, npy), and the ray window (i0, i1, j0, j1), the whole grid by default."""
+    sx0, sy0, sw, sh, nx, ny = shoot
+    tx0, ty0, tw, th, npx, npy = src
+    i0, i1, j0, j1 = (0, int(nx), 0, int(ny)) if window is None else (int(v) for v in window)
+    return dict(sigma_star=float(sigma_star), sigma_c=float(sigma_c), gamma=float(gamma),
+                sx0=float(sx0), sy0=float(sy0), sw=float(sw), sh=float(sh), nx=int(nx), ny=int(ny),
+                i0=i0, i1=i1, j0=j0, j1=j1,
+                tx0=float(tx0), ty0=float(ty0), tw=float(tw), th=float(th), npx=int(npx), npy=int(npy))
+
+
+def shoot_map(lens_xy, masses, sigma_star: float, sigma_c: float, gamma: float, shoot, src,
+              mode: str = "mixed", **kwargs):
+    """make_map with the model and grids given directly: lens positions [N, 2] and masses [N]
+    (None for unit masses), sigma_star, sigma_c, gamma, shoot = (x0, y0, w, h, nx, ny) and
+    src = (x0, y0, w, h, npx, npy). Returns the uint32 [npy, npx] count map; keyword
+    arguments go to make_map."""
+    return make_map(map_params(sigma_star, sigma_c, gamma, shoot, src), lens_xy, masses, mode=mode, **kwargs)
+
+
 def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optional[torch.Tensor] = None,
              workspace: Optional[torch.Tensor] = None, accumulate: bool = False, stream=None,
              return_stats: bool = False, exact_recheck: bool = False):

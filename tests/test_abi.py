@@ -179,3 +179,13 @@ def test_farfield_mode_validation(lib):
     assert b"regular grid" in lib.rs_last_error()
     req = L.MapRequest(c, 1 << 20, None, s.n_lens, 1 << 21)
     assert lib.rs_make_maps(ctypes.byref(req), 1, 1 << 22, 1 << 40, None) == L.RS_EINVAL
+
+
+def test_map_params_matches_the_generator():
+    """The binding's parameter packing equals the input generator's (the same fields and values)."""
+    from paper_1005_5198_amd import api, workloads as w
+    shoot, src = (-120.0, -24.0, 240.0, 48.0, 19200, 3840), (-10.0, -10.0, 20.0, 20.0, 1024, 1024)
+    assert api.map_params(0.8, 0.1, 0.3, shoot, src) == w.make_params(0.8, 0.1, 0.3, shoot, src)
+    win = (5, 700, 32, 64)
+    assert api.map_params(0.8, 0.1, 0.3, shoot, src, win) == w.make_params(0.8, 0.1, 0.3, shoot, src, win)
+    assert api.to_params(api.map_params(0.8, 0.1, 0.3, shoot, src)).npx == 1024

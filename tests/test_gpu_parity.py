@@ -205,6 +205,21 @@ def test_shared_reciprocal_range_guards(rs):
     assert st["rays_rechecked"] == 128 * 64 and st["rays_in_map"] > 0
 
 
+def test_shoot_map_signature(rs):
+    """shoot_map (model and grids given directly) gives the oracle's map, with and without masses."""
+    s = w.config0()
+    shoot = (-20.0, -20.0, 40.0, 40.0, 1024, 1024)
+    src = (-10.0, -10.0, 20.0, 20.0, 256, 256)
+    assert rs.map_params(0.4, 0.0, 0.0, shoot, src) == s.params
+    m_o, _ = oracle.make_map(s.params, s.lens_xy)
+    got = rs.shoot_map(s.lens_xy, None, 0.4, 0.0, 0.0, shoot, src).cpu().numpy()
+    assert np.array_equal(got, m_o)
+    masses = np.full(s.n_lens, 0.5)
+    m_o2, _ = oracle.make_map(s.params, s.lens_xy, masses)
+    got2 = rs.shoot_map(s.lens_xy, masses, 0.4, 0.0, 0.0, shoot, src).cpu().numpy()
+    assert np.array_equal(got2, m_o2)
+
+
 def test_empty_window(rs):
     s = w.config0().window(10, 10, 0, 1024)
     m_g, st = gpu_map(rs, s, "mixed")
