@@ -78,7 +78,8 @@ extern "C" {
 #define RS_EINVAL (-1)     /* bad argument (sizes, extents, window, null pointer, mode) */
 #define RS_ENOMEM (-2)     /* workspace too small, or server budget cannot hold a request */
 #define RS_EHIP (-3)       /* a HIP runtime call failed */
-#define RS_EBUSY (-4)      /* server full (non-blocking submit) */
+#define RS_EBUSY (-4)      /* reserved for a full server queue; not returned: rs_server_submit
+                              never blocks and its waiting queue has no bound */
 #define RS_ECANCELED (-5)  /* request cancelled */
 
 #define RS_FP32 0
