@@ -93,3 +93,24 @@ def lattice_count_1d(coef: F, s0: F, width: F, n: int, t0: F, tw: F, npix: int):
         else:
             out += 1
     return counts, out
+
+
+def near_edge_rays(p: dict, lenses, masses, tol: F):
+    """Sorted (i, j) of the window's rays whose exact source position lies within tol
+    (strictly) of a pixel edge that matters: both coordinates within [-tol, n + tol] of the
+    map, and u or v closer than tol to an integer (the integers 0..n bound the pixels and
+    the map). Singular rays are not listed. A ray off the map by more than tol on either
+    axis stays out whatever happens on the other, so it is not listed either."""
+    tol = F(tol)
+    listed = []
+    for j in range(p["j0"], p["j1"]):
+        for i in range(p["i0"], p["i1"]):
+            r = source_position(p, lenses, masses, i, j)
+            if r is None:
+                continue
+            u, v = r
+            if not (-tol <= u <= p["npx"] + tol and -tol <= v <= p["npy"] + tol):
+                continue
+            if edge_distance(u) < tol or edge_distance(v) < tol:
+                listed.append((i, j))
+    return sorted(listed)

@@ -212,6 +212,7 @@ def pin_brute_force(orc, seeds=(0, 1, 2, 3)):
         if min_edge is not None and min_edge > F(1, 10 ** 9):
             assert np.array_equal(m.astype(np.int64), expect), f"brute force mismatch seed {seed}"
             assert st["rays_out"] == out and st["rays_singular"] == sing
+            assert st["near_edge"] == 0
         else:
             diff = int(np.abs(m.astype(np.int64) - expect).sum())
             assert diff <= 2 * max(st["near_edge"], 1), f"brute force (near-edge case) seed {seed}"
@@ -227,6 +228,50 @@ def pin_singular(orc):
     assert sing == 1 and st["rays_singular"] == 1
     pix, _, _ = orc.ray_pixels(p, lens)
     assert pix[5 * 16 + 5] == -2
+
+
+# ---------------------------------------------------------------------------
+# Pin 8: the near-edge list (the rays the mixed-precision comparison may
+# exclude). With no lenses and unit macro terms every FP64 operation below is
+# exact, so the oracle's list must equal the exact-rational list. A dyadic
+# tolerance lets rays sit just inside (d = tol/2), exactly at (d = tol) and
+# just outside (d = 2 tol) the tolerance, below (k - d) and above (k + d) the
+# edges, on the borders 0 and n of the map, on one axis or both.
+# ---------------------------------------------------------------------------
+def _edge_grid(du, dv):
+    """1-px source pixels over [0, 8)^2 and a 48 x 48 ray grid at spacing 1/4 (unlensed,
+    u = x1, v = x2). An axis given an offset d has every fourth ray at k + d for
+    k = -1 .. 10 (the others a quarter pixel away); None puts every ray 1/16 px or more
+    from an edge; both axes reach beyond the map."""
+    def origin(d):
+        return -2.0 + 1.0 / 16 if d is None else -1.125 + d
+    return _p(0.0, 0.0, (origin(du), origin(dv), 12.0, 12.0, 48, 48), (0.0, 0.0, 8.0, 8.0, 8, 8))
+
+
+def pin_near_edge(orc):
+    tol = 2.0 ** -30
+    half, at, twice = 2.0 ** -31, 2.0 ** -30, 2.0 ** -29
+    cases = [
+        (None, -half, True), (None, -at, False), (None, -twice, False),   # v just below edges
+        (None, half, True), (None, at, False), (None, twice, False),      # v just above edges
+        (-half, None, True), (half, None, True), (-at, None, False),      # u only
+        (half, -half, True), (0.0, None, True), (None, None, False),
+    ]
+    for du, dv, nonempty in cases:
+        p = _edge_grid(du, dv)
+        _, st = orc.make_map(p, NO_LENS, near_tol=tol, near_cap=48 * 48)
+        expect = exact_ref.near_edge_rays(p, [], None, F(tol))
+        assert bool(expect) == nonempty, ("case design", du, dv)
+        got = sorted(tuple(int(x) for x in r) for r in st["near_edge_rays"])
+        assert st["near_edge"] == len(expect) and got == expect, \
+            f"near-edge list differs at du={du} dv={dv}: {st['near_edge']} listed, {len(expect)} expected"
+    # the map border at 0 and n is covered: rays at -d and n - d (below), n + d (above)
+    p = _edge_grid(None, half)
+    rows = {j for _, j in exact_ref.near_edge_rays(p, [], None, F(tol))}
+    assert 36 in rows and 0 not in rows       # v = 8 + d listed, v = -1 + d not
+    p = _edge_grid(None, -half)
+    rows = {j for _, j in exact_ref.near_edge_rays(p, [], None, F(tol))}
+    assert 4 in rows and 36 in rows and 40 not in rows   # v = -d and 8 - d listed, 9 - d not
 
 
 # ---------------------------------------------------------------------------
@@ -351,4 +396,5 @@ ALL_PINS = {
     "conservation": pin_conservation,
     "brute_force": pin_brute_force,
     "singular": pin_singular,
+    "near_edge": pin_near_edge,
 }

@@ -1,6 +1,7 @@
 """Pin sensitivity: plausible mistakes planted in copies of the oracle must fail a pin.
 
-Each mutant (15 on the lens equation and the grid, 7 on the random rays) is a one-line textual change to a temporary copy of oracle.c,
+Each mutant (15 on the lens equation and the grid, 7 on the random rays, 6 on the
+near-edge list) is a one-line textual change to a temporary copy of oracle.c,
 compiled on the CPU into a temporary library. The committed oracle is never
 modified. The unmutated source must pass every pin (test_oracle_pins.py).
 """
@@ -42,6 +43,13 @@ MUTANTS = {
     "uniform_reused": ("const double u2 = ((double)(out[1] >> 12) + 0.5) * 0x1p-52;",
                        "const double u2 = ((double)(out[0] >> 12) + 0.5) * 0x1p-52;"),
     "counter_transposed": ("(uint64_t)j * (uint64_t)p->nx + (uint64_t)i", "(uint64_t)i * (uint64_t)p->ny + (uint64_t)j"),
+    "near_edge_one_sided": ("const double d = fmin(c - f, f + 1.0 - c);", "const double d = c - f;"),
+    "near_edge_closed_tol": ("return d < tol;", "return d <= tol;"),
+    "near_edge_u_only": ("return near_edge_1d(r->u, p->npx, tol) || near_edge_1d(r->v, p->npy, tol);",
+                         "return near_edge_1d(r->u, p->npx, tol);"),
+    "near_edge_v_range_ignored": ("if (!in_u || !in_v)\n        return 0;", "if (!in_u)\n        return 0;"),
+    "near_edge_upper_border_open": ("r->u <= (double)p->npx + tol;", "r->u < (double)p->npx;"),
+    "near_edge_lower_border_open": ("const int in_v = r->v >= -tol", "const int in_v = r->v >= 0.0"),
 }
 
 
