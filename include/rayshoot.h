@@ -132,7 +132,8 @@ const char *rs_last_error(void);
  * re-check queue (4 bytes per ray of the largest launch, up to 2^27 rays) and
  * the super-patch records of the far-field expansion or re-check stage (about
  * 16.7 KB per 32768 rays); for random rays the bin arrays and the sorted ray
- * list (20 bytes per ray of the largest launch, up to 2^26 rays).
+ * list (20 bytes per ray of the largest launch, up to 2^26 rays or one 32-row
+ * band of a wider window). Windows wider than 2^22 rays are refused (RS_EINVAL).
  * Returns 0 if the parameters are invalid.
  */
 size_t rs_workspace_bytes(const rs_map_params *params, int64_t n_lens);
@@ -332,7 +333,7 @@ int rs_server_get_stats(rs_server *server, rs_server_stats *stats);
 void rs_server_destroy(rs_server *server);
 
 /* ---------------------------------------------------------------------------
- * Map statistics (Section 4, accuracy assessment; Eq. deltam; Section 2, Eq. mu).
+ * Map statistics (Section 3.1, Accuracy: the RMS and K-S assessment; Eq. deltam; Section 2, Eq. mu).
  *
  * A count map N (uint32, npix pixels, any layout: every statistic here is over
  * the set of pixels) gives the magnification mu = N / N_rays and the change in

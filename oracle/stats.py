@@ -3,7 +3,7 @@
 Only tests, the smoke check and the bench's CPU-baseline leg import this
 module. It shares nothing with the HIP product path.
 
-What the paper defines (Section 4, accuracy; Eq. deltam; Section 2, Eq. mu):
+What the paper defines (Section 3.1, Accuracy; Eq. deltam; Section 2, Eq. mu):
   * the magnification of pixel (i, j) is the number of rays it received
     divided by the average number of rays per pixel without lensing,
     mu_ij = N_ij / N_rays;

@@ -64,6 +64,17 @@ def _stream_handle(stream) -> Optional[int]:
     return s.cuda_stream or None
 
 
+def _hold(stream, *tensors) -> None:
+    """Tensors made on the current stream but used by the library on another stream:
+    tell the caching allocator, so that their memory is not handed out again before
+    that stream's work on them has finished."""
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def workspace_bytes(params: dict, n_lens: int, mode: str = "mixed") -> int:
     c = to_params(params, mode)
     n = L.lib().rs_workspace_bytes(ctypes.byref(c), int(n_lens))
@@ -118,6 +129,7 @@ def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optio
     h = _stream_handle(stream)
     L.check(L.lib().rs_make_map(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], out.data_ptr(),
                                 workspace.data_ptr(), workspace.numel(), h))
+    _hold(stream, xy, m, out, workspace)
     if return_stats:
         return out, read_stats(workspace, stream)
     return out
@@ -159,6 +171,7 @@ def profile_read():
     L.check(L.lib().rs_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(inter)))
     return ms.value, n.value, inter.value
 
+    _hold(stream, xy, m, pix, workspace)
 
 def version() -> str:
     return L.lib().rs_version().decode()
@@ -198,6 +211,7 @@ def tune_load(path: str) -> None:
 
 class Batch:
     """Device-resident inputs and outputs of a batch of maps, reusable across launches.
+    _hold(stream, xy, m, scratch, ws)
 
     maps: list of (params dict, lens_xy, lens_m or None). All maps share ``mode``.
     """
@@ -256,6 +270,7 @@ class Server:
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_inflight: int = 16, mode: str = "mixed",
                  slice_ms: float = 10.0, starve_s: float = 0.5):
         _device()
+        _hold(stream, self.workspace, *self.outs, *(t for pair in self.lenses for t in pair))
         cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms), float(starve_s))
         h = ctypes.c_void_p()
         L.check(L.lib().rs_server_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -316,7 +331,7 @@ class Server:
 
 
 # ---------------------------------------------------------------------------
-# Map statistics (Section 4, accuracy assessment; Eq. deltam): dm per pixel,
+# Map statistics (Section 3.1, Accuracy: RMS and K-S assessment; Eq. deltam): dm per pixel,
 # count histograms, and the RMS / K-S comparison of two maps.
 # ---------------------------------------------------------------------------
 
@@ -367,6 +382,7 @@ def delta_m(counts: torch.Tensor, n_rays: float, stream=None) -> torch.Tensor:
                                _stream_handle(stream)))
     return dm
 
+    _hold(stream, counts, dst)
 
 def compare_workspace_bytes(max_a: int, max_b: int) -> int:
     """Workspace bytes of compare_maps for count bounds max_a, max_b."""
@@ -380,6 +396,7 @@ def compare_maps(map_a: torch.Tensor, map_b: torch.Tensor, n_rays_a: float, n_ra
     _count_map(map_a, "map_a")
     _count_map(map_b, "map_b")
     if map_a.numel() != map_b.numel():
+    _hold(stream, counts, hist)
         raise ValueError("maps differ in size")
     n_rays_b = n_rays_a if n_rays_b is None else n_rays_b
     if max_a is None:
@@ -389,8 +406,10 @@ def compare_maps(map_a: torch.Tensor, map_b: torch.Tensor, n_rays_a: float, n_ra
     need = compare_workspace_bytes(max_a, max_b)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=map_a.device)
+    _hold(stream, counts, dm)
     res = L.CompareResult()
     L.check(L.lib().rs_compare_maps(map_a.data_ptr(), map_b.data_ptr(), map_a.numel(), float(n_rays_a),
                                     float(n_rays_b), int(max_a), int(max_b), workspace.data_ptr(),
                                     workspace.numel(), ctypes.byref(res), _stream_handle(stream)))
     return res.as_dict()
+    _hold(stream, map_a, map_b, workspace)

@@ -197,7 +197,7 @@ def phi_fiducial_both(rs, band_rows: int = 2400) -> dict:
 
 def phi_fiducial(rs, rows: int = 64, full: bool = False, band_rows: int = 2400, mode: str = "mixed",
                  out_map: bool = False) -> dict:
-    """The 1e6-lens, 2500^2-pixel, 3.1e15-interaction map of Section 3.1's Phi_fiducial.
+    """The 1e6-lens, 2500^2-pixel, 3.1e15-interaction map of Section 2's Phi_fiducial (the cost model Phi).
 
     By default a band of `rows` ray rows through the middle of the map is timed
     (3.6e12 interactions at 64 rows) and the full map's time is projected from

@@ -1,4 +1,4 @@
-// Map statistics of the accuracy assessment (Section 4; Eq. deltam; Eq. mu):
+// Map statistics of the accuracy assessment (Section 3.1, Accuracy; Eq. deltam; Eq. mu):
 // per-pixel change in magnitude, the RMS of its difference between two maps,
 // the two-sample Kolmogorov-Smirnov statistic of the two dm distributions and
 // its probability, and the histogram of ray counts.

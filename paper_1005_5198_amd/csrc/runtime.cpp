@@ -83,7 +83,9 @@ int validate(const rs_map_params *p, int64_t n_lens) {
         return fail(RS_EINVAL, "ray window [%lld,%lld)x[%lld,%lld) outside the %lldx%lld grid", (long long)p->i0,
                     (long long)p->i1, (long long)p->j0, (long long)p->j1, (long long)p->nx, (long long)p->ny);
     if (p->nx >= (int64_t(1) << 52) || p->ny >= (int64_t(1) << 52)) return fail(RS_EINVAL, "ray grid too large");
-    if (p->i1 - p->i0 > (int64_t(1) << 26)) return fail(RS_EINVAL, "window wider than 2^26 rays");
+    // A launch holds at least one 32-row band, and the re-check queue keeps a launch's
+    // ray index below bit 30 (its two top bits mark entries): 32 * 2^22 = 2^27.
+    if (p->i1 - p->i0 > (int64_t(1) << 22)) return fail(RS_EINVAL, "window wider than 2^22 rays");
     if (p->mode != RS_FP32 && p->mode != RS_MIXED && p->mode != RS_FARFIELD)
         return fail(RS_EINVAL, "mode must be RS_FP32, RS_MIXED or RS_FARFIELD");
     if (p->mode == RS_FARFIELD && (p->flags & RS_RANDOM_RAYS))

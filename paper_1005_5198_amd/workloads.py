@@ -217,7 +217,7 @@ def paper_point(sigma: float, gamma: float, sigma_c: float = 0.0, n_pix_side: in
 
 def phi_fiducial(seed: int = 6, sigma_star: float = 0.45, n_star: int = 1_000_000, n_pix_side: int = 2500,
                  rays_per_px: float = 500.0) -> MapSpec:
-    """The Phi_fiducial scale of Section 3.1: 2500^2 pixels, N* = 1e6 lenses, 500 rays per pixel.
+    """The Phi_fiducial scale of Section 2 (the cost model Phi): 2500^2 pixels, N* = 1e6 lenses, 500 rays per pixel.
 
     sigma* = 0.45 in unit-mass lenses, no smooth matter, no shear. The disc holds
     N* = sigma* R^2 lenses; the map side L follows from the paper-rule radius

@@ -189,3 +189,20 @@ def test_map_params_matches_the_generator():
     win = (5, 700, 32, 64)
     assert api.map_params(0.8, 0.1, 0.3, shoot, src, win) == w.make_params(0.8, 0.1, 0.3, shoot, src, win)
     assert api.to_params(api.map_params(0.8, 0.1, 0.3, shoot, src)).npx == 1024
+
+
+def test_window_wider_than_2_22_refused(lib):
+    """A launch holds at least one 32-row band, and a launch's ray index must stay below the
+    re-check queue's mark bits (bit 30): windows wider than 2^22 rays are refused."""
+    from paper_1005_5198_amd import api, workloads as w
+    p = dict(w.config0().params)
+    p.update(nx=(1 << 22) + 64, i0=0, i1=(1 << 22) + 1, j0=0, j1=32)
+    c = api.to_params(p)
+    assert lib.rs_workspace_bytes(ctypes.byref(c), 462) == 0
+    assert b"2^22" in lib.rs_last_error()
+    p.update(i1=1 << 22)
+    c = api.to_params(p)
+    n = lib.rs_workspace_bytes(ctypes.byref(c), 462)
+    # one band of 32 rows: the queue's largest index is 32 * 2^22 - 1 < 2^30
+    assert 4 * 32 * (1 << 22) <= n < (1 << 30)
+

@@ -409,3 +409,34 @@ def test_batch_matches_single_and_oracle(rs):
                 if s.n_rays * s.n_lens < 3e9:
                     m_o, _ = oracle.make_map(s.params, s.lens_xy, s.lens_m)
                     assert np.array_equal(o.cpu().numpy(), m_o)
+
+
+def _delay(stream, seconds=0.2):
+    """Queue a bounded spin on the stream, so that work queued after it starts late."""
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(int(seconds * 2.4e9))
+
+
+def test_side_stream_temporaries_stay_alive(rs):
+    """make_map and make_maps on a stream other than the current one, with lens copies and
+    workspaces made inside the call: while that stream is held back, the current stream
+    allocates and overwrites memory; the maps must still equal the oracle's."""
+    s = torch.cuda.Stream()
+    spec = w.config0().window(0, 1024, 200, 840)
+    m_o, _ = oracle.make_map(spec.params, spec.lens_xy, spec.lens_m)
+    ws_bytes = rs.workspace_bytes(spec.params, spec.n_lens, "mixed")
+    _delay(s)
+    out = rs.make_map(spec.params, spec.lens_xy, spec.lens_m, mode="mixed", stream=s)
+    junk = [torch.full((ws_bytes,), 255, dtype=torch.uint8, device="cuda"),
+            torch.full((spec.n_lens * 2,), 1e30, dtype=torch.float64, device="cuda")]
+    specs = [w.config0().window(0, 512, 0, 512), w.config0().window(300, 1024, 100, 700)]
+    _delay(s)
+    outs = rs.make_maps([(x.params, x.lens_xy, x.lens_m) for x in specs], mode="mixed", stream=s)
+    junk += [torch.full((8 << 20,), 255, dtype=torch.uint8, device="cuda") for _ in range(4)]
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), m_o)
+    for x, o in zip(specs, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle.make_map(x.params, x.lens_xy, x.lens_m)[0]), x.name
+    del junk
+

@@ -1,4 +1,4 @@
-"""The 1e6-lens scale of Section 3.1's Phi_fiducial (2500^2 pixels, 3.1e15 interactions) on the
+"""The 1e6-lens scale of Section 2's Phi_fiducial (2500^2 pixels, 3.1e15 interactions) on the
 HIP path (needs an MI355X): sampled rays of the full geometry against the FP64 oracle, and one
 band of rows made in the launch configuration the benchmark times."""
 import sys

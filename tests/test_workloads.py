@@ -95,7 +95,7 @@ def test_config4_arrivals_are_poisson():
 
 
 def test_phi_fiducial_scale():
-    """Section 3.1's Phi_fiducial: N_FLOP N_pix N* N_rays = 10 x 2500^2 x 1e6 x 500 = 3.1e16."""
+    """Section 2's Phi_fiducial (the cost model Phi): N_FLOP N_pix N* N_rays = 10 x 2500^2 x 1e6 x 500 = 3.1e16."""
     s = w.phi_fiducial()
     assert s.n_lens == 1_000_000
     assert s.params["npx"] == s.params["npy"] == 2500
