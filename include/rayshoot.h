@@ -171,6 +171,32 @@ int rs_ray_pixels(const rs_map_params *params, const double *lens_xy, const doub
 int rs_read_stats(const void *workspace, rs_map_stats *stats_host, void *stream);
 
 /*
+ * rs_make_map without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops or harnesses that forbid hipMalloc).
+ * The same count map and counters as rs_make_map (same arguments, same errors),
+ * computed with a static device scratch of RS_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends, instead of a
+ * caller workspace; the map is built in launches of as many 32-row bands as the
+ * scratch holds (on the regular grid every mode gives rs_make_map's map bit for
+ * bit; with RS_RANDOM_RAYS the mixed mode does, while RS_FP32 may bin a few rays
+ * differently, as launches of other sizes sort rays into other bins). The call
+ * allocates nothing and never creates HIP events (rs_profile_enable does not
+ * apply to it).
+ *   stats_host  HOST; NULL, or filled with the call's counters after a device-to-host
+ *               copy and a synchronisation of the stream (pass NULL under graph
+ *               capture)
+ * The scratch is on the current device; the stream must belong to it. Every call
+ * on one device shares that device's scratch, which keeps the last call's contents
+ * (each call clears what must start at zero): calls that overlap on one device,
+ * on different streams or threads, race and corrupt each other's maps. Serialise them.
+ * Errors: as rs_make_map; RS_ENOMEM when one 32-row band of the window needs more
+ * than RS_NOALLOC_SCRATCH_BYTES (a window wider than about 500000 rays in RS_MIXED).
+ */
+#define RS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int rs_make_map_noalloc(const rs_map_params *params, const double *lens_xy, const double *lens_m,
+                        int64_t n_lens, uint32_t *map, rs_map_stats *stats_host, void *stream);
+
+/*
  * Kernel timing. When enabled, rs_make_map records HIP events on its stream
  * around every deflection-kernel launch; rs_profile_read synchronises those
  * events and returns the summed kernel milliseconds, the number of launches

@@ -6,6 +6,7 @@ Public entry points (loaded lazily so that importing the package, e.g. for
     make_map(params, lens_xy, lens_m=None, mode="mixed") -> torch.uint32 [npy, npx]
     shoot_map(lens_xy, masses, sigma_star, sigma_c, gamma, shoot, src, mode="mixed")
                                           the same with the model and grids given directly
+    make_map_noalloc(params, lens_xy, ...)  make_map with no device allocation in the library
     ray_pixels(params, lens_xy, lens_m=None, mode="mixed") -> torch.int32 [rays in window]
     read_stats(workspace) -> dict
     make_maps(maps) / Batch / Server      many maps: one persistent launch; a request loop
@@ -15,7 +16,7 @@ Public entry points (loaded lazily so that importing the package, e.g. for
 ``params`` is a dict with the fields of ``rs_map_params`` (see include/rayshoot.h);
 ``map_params(sigma_star, sigma_c, gamma, shoot, src)`` builds one.
 """
-_API = ("make_map", "shoot_map", "map_params", "ray_pixels", "read_stats", "workspace_bytes", "new_workspace", "to_params",
+_API = ("make_map", "make_map_noalloc", "shoot_map", "map_params", "ray_pixels", "read_stats", "workspace_bytes", "new_workspace", "to_params",
         "lens_tensors", "profile_enable", "profile_read", "version", "tune", "set_shape", "tune_save",
         "tune_load", "make_maps", "Batch", "Server", "rays_per_pixel", "map_max", "histogram", "delta_m",
         "compare_maps", "compare_workspace_bytes")

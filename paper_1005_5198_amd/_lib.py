@@ -23,6 +23,7 @@ RS_FARFIELD = 2
 RS_ACCUMULATE = 1
 RS_EXACT_RECHECK = 2
 RS_RANDOM_RAYS = 4
+RS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _ERRNAMES = {RS_EINVAL: "RS_EINVAL", RS_ENOMEM: "RS_ENOMEM", RS_EHIP: "RS_EHIP",
              RS_EBUSY: "RS_EBUSY", RS_ECANCELED: "RS_ECANCELED"}
@@ -111,6 +112,7 @@ def _declare(lib):
         "rs_make_map": ([P(MapParams), VP, VP, I64, VP, VP, SZ, VP], INT),
         "rs_ray_pixels": ([P(MapParams), VP, VP, I64, VP, VP, SZ, VP], INT),
         "rs_read_stats": ([VP, P(MapStats), VP], INT),
+        "rs_make_map_noalloc": ([P(MapParams), VP, VP, I64, VP, P(MapStats), VP], INT),
         "rs_profile_enable": ([INT], INT),
         "rs_profile_read": ([P(ctypes.c_double), P(I64), P(ctypes.c_double)], INT),
         "rs_tune": ([P(MapParams), VP, VP, I64, VP, VP, SZ, I64, VP, P(TuneResult)], INT),
@@ -162,7 +164,7 @@ def check(rc: int) -> None:
 def exported_symbols():
     """Names of the C-ABI functions this binding declares."""
     return ["rs_version", "rs_last_error", "rs_workspace_bytes", "rs_make_map", "rs_ray_pixels",
-            "rs_read_stats", "rs_profile_enable", "rs_profile_read", "rs_tune", "rs_set_shape",
+            "rs_read_stats", "rs_make_map_noalloc", "rs_profile_enable", "rs_profile_read", "rs_tune", "rs_set_shape",
             "rs_tune_save", "rs_tune_load", "rs_batch_workspace_bytes", "rs_make_maps",
             "rs_batch_read_stats", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
             "rs_server_cancel", "rs_server_get_stats", "rs_server_destroy", "rs_rays_per_pixel", "rs_map_max",

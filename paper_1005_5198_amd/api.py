@@ -135,6 +135,30 @@ def make_map(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optio
     return out
 
 
+def make_map_noalloc(params: dict, lens_xy, lens_m=None, mode: str = "mixed", out: Optional[torch.Tensor] = None,
+                     accumulate: bool = False, stream=None, return_stats: bool = False,
+                     exact_recheck: bool = False):
+    """make_map through the entry point that allocates nothing on the device: the library
+    uses its static per-device scratch instead of a workspace. Calls that overlap on one
+    device race (they share that scratch). With return_stats it synchronises and also
+    returns the counters. Pass device tensors for the lenses and ``out`` to keep the
+    binding itself from allocating."""
+    dev = _device()
+    xy, m = lens_tensors(lens_xy, lens_m, dev)
+    c = to_params(params, mode, accumulate, exact_recheck)
+    if out is None:
+        out = torch.empty((int(params["npy"]), int(params["npx"])), dtype=torch.uint32, device=dev)
+    if out.dtype != torch.uint32 or not out.is_contiguous() or tuple(out.shape) != (c.npy, c.npx):
+        raise ValueError("out must be a contiguous uint32 tensor of shape (npy, npx)")
+    st = L.MapStats() if return_stats else None
+    L.check(L.lib().rs_make_map_noalloc(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], out.data_ptr(),
+                                        ctypes.byref(st) if st is not None else None, _stream_handle(stream)))
+    _hold(stream, xy, m, out)
+    if return_stats:
+        return out, st.as_dict()
+    return out
+
+
 def ray_pixels(params: dict, lens_xy, lens_m=None, mode: str = "mixed", workspace=None, stream=None,
                return_stats: bool = False, exact_recheck: bool = False):
     """Per-ray pixel index int32 over the window (row-major): v*npx+u, -1 out, -2 singular."""
@@ -147,6 +171,7 @@ def ray_pixels(params: dict, lens_xy, lens_m=None, mode: str = "mixed", workspac
         workspace = new_workspace(params, xy.shape[0], mode, dev)
     L.check(L.lib().rs_ray_pixels(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], pix.data_ptr(),
                                   workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+    _hold(stream, xy, m, pix, workspace)
     pix = pix[:n]
     if return_stats:
         return pix, read_stats(workspace, stream)
@@ -171,7 +196,6 @@ def profile_read():
     L.check(L.lib().rs_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(inter)))
     return ms.value, n.value, inter.value
 
-    _hold(stream, xy, m, pix, workspace)
 
 def version() -> str:
     return L.lib().rs_version().decode()
@@ -187,6 +211,7 @@ def tune(params: dict, lens_xy, lens_m=None, mode: str = "mixed", sample_rays: i
     r = L.TuneResult()
     L.check(L.lib().rs_tune(ctypes.byref(c), _ptr(xy), _ptr(m), xy.shape[0], scratch.data_ptr(), ws.data_ptr(),
                             ws.numel(), int(sample_rays), _stream_handle(stream), ctypes.byref(r)))
+    _hold(stream, xy, m, scratch, ws)
     shapes = [dict(shape=k, rays_per_lane=(r.rays_per_lane[k][0], r.rays_per_lane[k][1]),
                    threads=r.threads[k], ms=r.ms[k],
                    interactions_per_s=r.sample_interactions / (r.ms[k] * 1e-3) if r.ms[k] > 0 else 0.0)
@@ -211,7 +236,6 @@ def tune_load(path: str) -> None:
 
 class Batch:
     """Device-resident inputs and outputs of a batch of maps, reusable across launches.
-    _hold(stream, xy, m, scratch, ws)
 
     maps: list of (params dict, lens_xy, lens_m or None). All maps share ``mode``.
     """
@@ -246,6 +270,7 @@ class Batch:
         """Enqueue every map of the batch (asynchronous)."""
         L.check(L.lib().rs_make_maps(self.reqs, len(self.params), self.workspace.data_ptr(),
                                      self.workspace.numel(), _stream_handle(stream)))
+        _hold(stream, self.workspace, *self.outs, *(t for pair in self.lenses for t in pair))
         return self.outs
 
     def stats(self, stream=None):
@@ -270,7 +295,6 @@ class Server:
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_inflight: int = 16, mode: str = "mixed",
                  slice_ms: float = 10.0, starve_s: float = 0.5):
         _device()
-        _hold(stream, self.workspace, *self.outs, *(t for pair in self.lenses for t in pair))
         cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms), float(starve_s))
         h = ctypes.c_void_p()
         L.check(L.lib().rs_server_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -358,6 +382,7 @@ def map_max(counts: torch.Tensor, stream=None, out: Optional[torch.Tensor] = Non
     _count_map(counts)
     dst = out if out is not None else torch.empty(1, dtype=torch.int32, device=counts.device)
     L.check(L.lib().rs_map_max(counts.data_ptr(), counts.numel(), dst.data_ptr(), _stream_handle(stream)))
+    _hold(stream, counts, dst)
     if out is not None:
         return out
     return int(dst.item()) & 0xFFFFFFFF
@@ -371,6 +396,7 @@ def histogram(counts: torch.Tensor, max_count: Optional[int] = None, stream=None
     hist = torch.empty(int(max_count) + 2, dtype=torch.int64, device=counts.device)
     L.check(L.lib().rs_map_histogram(counts.data_ptr(), counts.numel(), int(max_count), hist.data_ptr(),
                                      _stream_handle(stream)))
+    _hold(stream, counts, hist)
     return hist
 
 
@@ -380,9 +406,9 @@ def delta_m(counts: torch.Tensor, n_rays: float, stream=None) -> torch.Tensor:
     dm = torch.empty(counts.shape, dtype=torch.float64, device=counts.device)
     L.check(L.lib().rs_delta_m(counts.data_ptr(), counts.numel(), float(n_rays), dm.data_ptr(),
                                _stream_handle(stream)))
+    _hold(stream, counts, dm)
     return dm
 
-    _hold(stream, counts, dst)
 
 def compare_workspace_bytes(max_a: int, max_b: int) -> int:
     """Workspace bytes of compare_maps for count bounds max_a, max_b."""
@@ -396,7 +422,6 @@ def compare_maps(map_a: torch.Tensor, map_b: torch.Tensor, n_rays_a: float, n_ra
     _count_map(map_a, "map_a")
     _count_map(map_b, "map_b")
     if map_a.numel() != map_b.numel():
-    _hold(stream, counts, hist)
         raise ValueError("maps differ in size")
     n_rays_b = n_rays_a if n_rays_b is None else n_rays_b
     if max_a is None:
@@ -406,10 +431,9 @@ def compare_maps(map_a: torch.Tensor, map_b: torch.Tensor, n_rays_a: float, n_ra
     need = compare_workspace_bytes(max_a, max_b)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=map_a.device)
-    _hold(stream, counts, dm)
     res = L.CompareResult()
     L.check(L.lib().rs_compare_maps(map_a.data_ptr(), map_b.data_ptr(), map_a.numel(), float(n_rays_a),
                                     float(n_rays_b), int(max_a), int(max_b), workspace.data_ptr(),
                                     workspace.numel(), ctypes.byref(res), _stream_handle(stream)))
-    return res.as_dict()
     _hold(stream, map_a, map_b, workspace)
+    return res.as_dict()

@@ -96,7 +96,8 @@ int validate(const rs_map_params *p, int64_t n_lens) {
     return RS_OK;
 }
 
-Plan make_plan(const rs_map_params *p) {
+// rows_override > 0 (a multiple of PATCH_Y) replaces the default rows per launch.
+Plan make_plan(const rs_map_params *p, int64_t rows_override = 0) {
     Plan pl;
     pl.W = p->i1 - p->i0;
     pl.H = p->j1 - p->j0;
@@ -105,6 +106,7 @@ Plan make_plan(const rs_map_params *p) {
     int64_t rows = pl.W > 0 ? chunk_rays / pl.W : PATCH_Y;
     rows = rows / PATCH_Y * PATCH_Y;
     if (rows < PATCH_Y) rows = PATCH_Y;
+    if (rows_override > 0) rows = rows_override;
     pl.rows_per_chunk = rows;
     pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
     const int64_t rows_cap = pl.H < rows ? pl.H : rows;
@@ -156,6 +158,30 @@ Plan make_plan(const rs_map_params *p) {
         pl.bytes = off;
     }
     return pl;
+}
+
+// The plan with the most rows per launch (a multiple of PATCH_Y, at most the default)
+// whose workspace fits max_bytes; the workspace grows with the rows per launch.
+// Returns false when a single band of PATCH_Y rows does not fit.
+bool plan_within(const rs_map_params *p, size_t max_bytes, Plan &out) {
+    out = make_plan(p);
+    if (out.bytes <= max_bytes) return true;
+    int64_t lo = 1, hi = out.rows_per_chunk / PATCH_Y - 1;   // bands per launch
+    Plan best = make_plan(p, PATCH_Y);
+    if (best.bytes > max_bytes) return false;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        Plan t = make_plan(p, mid * PATCH_Y);
+        if (t.bytes <= max_bytes) {
+            lo = mid;
+            best = t;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (best.rows_per_chunk != lo * PATCH_Y) best = make_plan(p, lo * PATCH_Y);
+    out = best;
+    return true;
 }
 
 struct Profile {
@@ -235,19 +261,58 @@ int choose_shape(int mode, bool unit, int64_t n_lens);
 // Enqueue the whole map (or pixel) computation. map may be null when pix is set.
 // shape < 0 picks the tuned or default thread shape. When kernel_ms is given,
 // the deflection launches are timed with events and the call synchronises.
-int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
-                uint32_t *map, int32_t *pix, void *workspace, size_t workspace_bytes, hipStream_t stream,
-                int shape, float *kernel_ms) {
+static int check_inputs(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                        const uint32_t *map, const int32_t *pix) {
     int rc = validate(p, n_lens);
     if (rc) return rc;
     if (n_lens > 0 && !lens_xy) return fail(RS_EINVAL, "lens_xy is NULL");
     if (!map && !pix) return fail(RS_EINVAL, "output is NULL");
-    if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(lens_xy) | reinterpret_cast<uintptr_t>(lens_m)) & 7)
         return fail(RS_EINVAL, "lens arrays must be 8-byte aligned");
+    return RS_OK;
+}
+
+static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                           uint32_t *map, int32_t *pix, void *workspace, hipStream_t stream, int shape,
+                           float *kernel_ms, const Plan &pl, bool profile);
+
+int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                uint32_t *map, int32_t *pix, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                int shape, float *kernel_ms) {
+    int rc = check_inputs(p, lens_xy, lens_m, n_lens, map, pix);
+    if (rc) return rc;
+    if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
     const Plan pl = make_plan(p);
     if (workspace_bytes < pl.bytes)
         return fail(RS_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, pl.bytes);
+    return enqueue_planned(p, lens_xy, lens_m, n_lens, map, pix, workspace, stream, shape, kernel_ms, pl, true);
+}
+
+// The map in launches small enough for a fixed scratch buffer of scratch_bytes (the
+// entry point without allocation). The arguments are checked and the launches planned
+// before scratch_of_device gives the buffer's device address. Profiling events are never
+// created here.
+int enqueue_map_fixed(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                      uint32_t *map, int (*scratch_of_device)(void **), size_t scratch_bytes,
+                      hipStream_t stream, void **scratch_used) {
+    int rc = check_inputs(p, lens_xy, lens_m, n_lens, map, nullptr);
+    if (rc) return rc;
+    if (!map) return fail(RS_EINVAL, "map is NULL");
+    Plan pl;
+    if (!plan_within(p, scratch_bytes, pl))
+        return fail(RS_ENOMEM, "one band of %d rows of this window needs %zu bytes of scratch; the static "
+                    "scratch holds %zu", PATCH_Y, make_plan(p, PATCH_Y).bytes, scratch_bytes);
+    void *scratch = nullptr;
+    rc = scratch_of_device(&scratch);
+    if (rc) return rc;
+    *scratch_used = scratch;
+    return enqueue_planned(p, lens_xy, lens_m, n_lens, map, nullptr, scratch, stream, -1, nullptr, pl, false);
+}
+
+static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const double *lens_m, int64_t n_lens,
+                           uint32_t *map, int32_t *pix, void *workspace, hipStream_t stream, int shape,
+                           float *kernel_ms, const Plan &pl, bool profile) {
+    int rc = RS_OK;
 
     const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
     hipError_t e =
@@ -352,7 +417,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
             a.ff_j0 = a.jc0;
         }
         ProfileToken tok;
-        profile_begin(stream, &tok.tok);
+        if (profile) profile_begin(stream, &tok.tok);
         if (kernel_ms && hipEventRecord(ev.first, stream) != hipSuccess) return fail(RS_EHIP, "hipEventRecord failed");
         if (pl.random) {
             random_bins((a.jc1 - a.jc0) * pl.W, p->sw, p->sh, a.nbx_r, a.nby_r);

@@ -206,3 +206,28 @@ def test_window_wider_than_2_22_refused(lib):
     # one band of 32 rows: the queue's largest index is 32 * 2^22 - 1 < 2^30
     assert 4 * 32 * (1 << 22) <= n < (1 << 30)
 
+
+def test_noalloc_entry_point_rejects_before_device_work(lib):
+    """rs_make_map_noalloc validates and plans before it looks up its scratch on the device:
+    bad parameters give RS_EINVAL, and a window one 32-row band of which does not fit the
+    static scratch gives RS_ENOMEM (the pointers are never dereferenced: nothing is launched)."""
+    from paper_1005_5198_amd import api, _lib, workloads as w
+    s = w.config0()
+    bad = dict(s.params)
+    bad["npx"] = 0
+    c = api.to_params(bad)
+    assert lib.rs_make_map_noalloc(ctypes.byref(c), None, None, 0, None, None, None) == _lib.RS_EINVAL
+    c = api.to_params(s.params)
+    assert lib.rs_make_map_noalloc(ctypes.byref(c), None, None, 0, None, None, None) == _lib.RS_EINVAL
+    assert b"NULL" in lib.rs_last_error()
+    wide = dict(s.params)
+    wide.update(nx=1 << 22, i0=0, i1=1 << 22, j0=0, j1=64)
+    c = api.to_params(wide)
+    fake = ctypes.c_void_p(1 << 20)   # an aligned, non-null address that is never used
+    rc = lib.rs_make_map_noalloc(ctypes.byref(c), fake, None, 462, fake, None, None)
+    assert rc == _lib.RS_ENOMEM
+    assert b"scratch" in lib.rs_last_error()
+    # the FP32 mode needs no queue: the same window plans within the scratch
+    c = api.to_params(wide, "fp32")
+    n = lib.rs_workspace_bytes(ctypes.byref(c), 462)
+    assert 0 < n <= _lib.RS_NOALLOC_SCRATCH_BYTES
