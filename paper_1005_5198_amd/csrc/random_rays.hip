@@ -229,8 +229,8 @@ __device__ __forceinline__ void shoot_free_chunk(const ShootArgs &a, uint32_t ba
         const double u = (y1 - a.tx0) * a.inv_pixw;
         const double v = (y2 - a.ty0) * a.inv_pixh;
         // reciprocals are shared between two lenses of one ray, not between rays
-        int code = classify_ray<MODE>(a, x1, x2, Ax[q], Ay[q], u, v, rx[q], ry[q], rx[q], ry[q], Bx, By, n_near,
-                                      all_flagged, sm.near_list, k_term, h_f, tiny_r2);
+        int code = classify_ray<MODE>(a, x1, x2, Ax[q], Ay[q], u, v, rx[q], ry[q], rx[q], ry[q], rx[q], false, Bx, By,
+                                      n_near, all_flagged, sm.near_list, k_term, h_f, tiny_r2);
         if (!valid) code = INT32_MIN;
 
         n_in += __builtin_popcountll(__ballot(code >= 0));

@@ -13,8 +13,9 @@
 //  * Each lane owns RX x RY rays (4x2, 4x4, 8x2 or 8x4: a tuned choice), its
 //    rows in adjacent pairs; per lens it computes dx for RX columns and dy,
 //    dy^2 for RY rows, then r^2 = fma(dx, dx, dy^2) per ray, one v_rcp_f32 per
-//    pair of rows (of the product of their r^2) and three multiplies, and two
-//    FMAs per ray. Every LDS read is a 16-byte broadcast of two lenses.
+//    four rays (two adjacent rows of two columns 16 apart, of the product of
+//    their r^2) and nine multiplies, and two FMAs per ray. Every LDS read is a
+//    16-byte broadcast of two lenses.
 //  * The sum runs in FP32 over GROUP lenses, then each partial is folded
 //    exactly into an FP64 accumulator, so FP32 rounding never sees the large
 //    running total.
@@ -29,19 +30,86 @@
 namespace rs {
 namespace {
 
-// FP32 sums over the N lenses of tile entries g .. g+N-1 for this lane's RX x RY
-// rays, folded into the FP64 accumulators: dx per column, dy and dy^2 per row,
-// then per ray r^2, the reciprocal and two FMAs. The rays of rows 2k and 2k+1 of
-// a column share one v_rcp_f32, of the product of their r^2 (1/a = b/(ab),
-// 1/b = a/(ab)): the reciprocal issues at a fraction of the FMA rate, and three
-// multiplies in place of a second one make the loop 9% faster. The partner row
-// does not depend on the thread shape, so neither does a ray's arithmetic. Every
-// LDS read is a 16-byte broadcast (two lenses of unit mass, or one lens with its
-// mass; the mass multiplies last, so a unit mass gives the unit path's result).
-template <int N, int RX, int RY, bool UNIT>
+// One lens's terms for this lane's RX x RY rays: dx per column, dy and dy^2 per
+// row, then per ray r^2 = fma(dx, dx, dy^2), the reciprocal and two FMAs into the
+// FP32 sums. The reciprocal issues at a fraction of the FMA rate, so rays share it
+// through products of their r^2:
+//  * QUAD: the rays of rows 2k, 2k+1 and columns c, c' = c + 16 (lane columns c
+//    and c + CQ, CQ = 16 / stride) share one v_rcp_f32 of P = (a b)(c d):
+//    1/a = b (R cd), 1/b = a (R cd), 1/c = d (R ab), 1/d = c (R ab) with
+//    R = rcp(P), nine multiplies per four rays;
+//  * otherwise rows 2k and 2k+1 of a column share one, of the product of their
+//    r^2 (1/a = b/(ab), 1/b = a/(ab)), three multiplies per two rays.
+// With masses each reciprocal is multiplied by the lens's mass last, so a unit
+// mass gives the unit path's result. The partners do not depend on the thread
+// shape, so neither does a ray's arithmetic.
+template <int RX, int RY, bool UNIT, bool QUAD, int CQ>
+__device__ __forceinline__ void lens_terms(float LX, float LY, float M, const float (&rxl)[RX],
+                                           const float (&ryl)[RY], float (&sx)[RY][RX], float (&sy)[RY][RX]) {
+    float dy[RY], dy2[RY], dx[RX];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        dy[r] = ryl[r] - LY;
+        dy2[r] = dy[r] * dy[r];
+    }
+#pragma unroll
+    for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - LX;
+#pragma unroll
+    for (int r = 0; r < RY; r += 2)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) {
+            if (QUAD) {
+                if ((c / CQ) % 2) continue;
+                const int e = c + CQ;
+                const float ra = __builtin_fmaf(dx[c], dx[c], dy2[r]);
+                const float rb = __builtin_fmaf(dx[c], dx[c], dy2[r + 1]);
+                const float rc = __builtin_fmaf(dx[e], dx[e], dy2[r]);
+                const float rd = __builtin_fmaf(dx[e], dx[e], dy2[r + 1]);
+                const float pab = ra * rb, pcd = rc * rd;
+                const float R = __builtin_amdgcn_rcpf(pab * pcd);
+                const float qab = R * pcd, qcd = R * pab;
+                float ia = rb * qab, ib = ra * qab, ic = rd * qcd, id = rc * qcd;
+                if (!UNIT) {
+                    ia = M * ia;
+                    ib = M * ib;
+                    ic = M * ic;
+                    id = M * id;
+                }
+                sx[r][c] = __builtin_fmaf(dx[c], ia, sx[r][c]);
+                sy[r][c] = __builtin_fmaf(dy[r], ia, sy[r][c]);
+                sx[r + 1][c] = __builtin_fmaf(dx[c], ib, sx[r + 1][c]);
+                sy[r + 1][c] = __builtin_fmaf(dy[r + 1], ib, sy[r + 1][c]);
+                sx[r][e] = __builtin_fmaf(dx[e], ic, sx[r][e]);
+                sy[r][e] = __builtin_fmaf(dy[r], ic, sy[r][e]);
+                sx[r + 1][e] = __builtin_fmaf(dx[e], id, sx[r + 1][e]);
+                sy[r + 1][e] = __builtin_fmaf(dy[r + 1], id, sy[r + 1][e]);
+            } else {
+                const float ra = __builtin_fmaf(dx[c], dx[c], dy2[r]);
+                const float rb = __builtin_fmaf(dx[c], dx[c], dy2[r + 1]);
+                const float rab = __builtin_amdgcn_rcpf(ra * rb);
+                float ia = rb * rab, ib = ra * rab;
+                if (!UNIT) {
+                    ia = M * ia;
+                    ib = M * ib;
+                }
+                sx[r][c] = __builtin_fmaf(dx[c], ia, sx[r][c]);
+                sy[r][c] = __builtin_fmaf(dy[r], ia, sy[r][c]);
+                sx[r + 1][c] = __builtin_fmaf(dx[c], ib, sx[r + 1][c]);
+                sy[r + 1][c] = __builtin_fmaf(dy[r + 1], ib, sy[r + 1][c]);
+            }
+        }
+}
+
+// FP32 sums over the N lenses of tile entries g .. g+N-1 for this lane's rays
+// (lens_terms), folded into the FP64 accumulators. Every LDS read is a 16-byte
+// broadcast: two lenses of unit mass, or one lens with its mass. The four-ray
+// loop is unrolled by 8 reads, not fully (a full unroll makes the compiler spill);
+// the two-ray loop fully.
+template <int N, int RX, int RY, bool UNIT, bool QUAD, int CQ>
 __device__ __forceinline__ void group_sums(const float4 *tile, int g, const float (&rxl)[RX], const float (&ryl)[RY],
                                            double (&Ax)[RY][RX], double (&Ay)[RY][RX]) {
     static_assert(RY % 2 == 0, "rows are paired for the shared reciprocal");
+    static_assert(RX == 4 * CQ, "column partners are CQ lane columns apart");
     float sx[RY][RX], sy[RY][RX];
 #pragma unroll
     for (int r = 0; r < RY; ++r)
@@ -51,63 +119,34 @@ __device__ __forceinline__ void group_sums(const float4 *tile, int g, const floa
             sy[r][c] = 0.0f;
         }
     if (UNIT) {
+        if (QUAD) {
+#pragma unroll 8
+            for (int kk = 0; kk < N; kk += 2) {
+                const float4 q = tile[(g + kk) >> 1];
+                lens_terms<RX, RY, true, true, CQ>(q.x, q.y, 1.0f, rxl, ryl, sx, sy);
+                lens_terms<RX, RY, true, true, CQ>(q.z, q.w, 1.0f, rxl, ryl, sx, sy);
+            }
+        } else {
 #pragma unroll
-        for (int kk = 0; kk < N; kk += 2) {
-            const float4 q = tile[(g + kk) >> 1];
-#pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const float LX = half ? q.z : q.x;
-                const float LY = half ? q.w : q.y;
-                float dy[RY], dy2[RY], dx[RX];
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    dy[r] = ryl[r] - LY;
-                    dy2[r] = dy[r] * dy[r];
-                }
-#pragma unroll
-                for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - LX;
-#pragma unroll
-                for (int r = 0; r < RY; r += 2)
-#pragma unroll
-                    for (int c = 0; c < RX; ++c) {
-                        const float ra = __builtin_fmaf(dx[c], dx[c], dy2[r]);
-                        const float rb = __builtin_fmaf(dx[c], dx[c], dy2[r + 1]);
-                        const float rab = __builtin_amdgcn_rcpf(ra * rb);
-                        const float ia = rb * rab, ib = ra * rab;
-                        sx[r][c] = __builtin_fmaf(dx[c], ia, sx[r][c]);
-                        sy[r][c] = __builtin_fmaf(dy[r], ia, sy[r][c]);
-                        sx[r + 1][c] = __builtin_fmaf(dx[c], ib, sx[r + 1][c]);
-                        sy[r + 1][c] = __builtin_fmaf(dy[r + 1], ib, sy[r + 1][c]);
-                    }
+            for (int kk = 0; kk < N; kk += 2) {
+                const float4 q = tile[(g + kk) >> 1];
+                lens_terms<RX, RY, true, false, CQ>(q.x, q.y, 1.0f, rxl, ryl, sx, sy);
+                lens_terms<RX, RY, true, false, CQ>(q.z, q.w, 1.0f, rxl, ryl, sx, sy);
             }
         }
     } else {
-        // the same pairing, each term times its lens's mass (a unit mass multiplies
-        // exactly, so unit-mass maps come out as on the unit path)
-#pragma unroll
-        for (int kk = 0; kk < N; ++kk) {
-            const float4 q = tile[g + kk];
-            float dy[RY], dy2[RY], dx[RX];
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                dy[r] = ryl[r] - q.y;
-                dy2[r] = dy[r] * dy[r];
+        if (QUAD) {
+#pragma unroll 8
+            for (int kk = 0; kk < N; ++kk) {
+                const float4 q = tile[g + kk];
+                lens_terms<RX, RY, false, true, CQ>(q.x, q.y, q.z, rxl, ryl, sx, sy);
             }
+        } else {
 #pragma unroll
-            for (int c = 0; c < RX; ++c) dx[c] = rxl[c] - q.x;
-#pragma unroll
-            for (int r = 0; r < RY; r += 2)
-#pragma unroll
-                for (int c = 0; c < RX; ++c) {
-                    const float ra = __builtin_fmaf(dx[c], dx[c], dy2[r]);
-                    const float rb = __builtin_fmaf(dx[c], dx[c], dy2[r + 1]);
-                    const float rab = __builtin_amdgcn_rcpf(ra * rb);
-                    const float ia = q.z * (rb * rab), ib = q.z * (ra * rab);
-                    sx[r][c] = __builtin_fmaf(dx[c], ia, sx[r][c]);
-                    sy[r][c] = __builtin_fmaf(dy[r], ia, sy[r][c]);
-                    sx[r + 1][c] = __builtin_fmaf(dx[c], ib, sx[r + 1][c]);
-                    sy[r + 1][c] = __builtin_fmaf(dy[r + 1], ib, sy[r + 1][c]);
-                }
+            for (int kk = 0; kk < N; ++kk) {
+                const float4 q = tile[g + kk];
+                lens_terms<RX, RY, false, false, CQ>(q.x, q.y, q.z, rxl, ryl, sx, sy);
+            }
         }
     }
 #pragma unroll
@@ -175,9 +214,15 @@ __device__ __forceinline__ void shoot_patch(const ShootArgs &a, int64_t patch, S
             Ay[r][c] = 0.0;
         }
 
-    if (tid == 0) near_count = 0;
+    if (tid == 0) {
+        near_count = 0;
+        sm.far_tile = -1;
+    }
     double bx = 0.0, by = 0.0;  // this thread's share of the block error bound (units of u)
-    const double k_term = UNIT ? K_TERM_UNIT : K_TERM_MASS;
+    const double k_term = UNIT ? K_TERM_QUAD : K_TERM_MASS_QUAD;
+    // Four-ray reciprocals need the patch's half-diagonal in range (see QUAD_RANGE).
+    const bool quad_patch = h >= QUAD_H_MIN && h <= QUAD_H_MAX;
+    constexpr int CQ = 16 / STRIDE_X;
 
     for (int64_t t0 = 0; t0 < a.n_lens; t0 += LENS_TILE) {
         const int cnt = (int)((a.n_lens - t0) < LENS_TILE ? (a.n_lens - t0) : LENS_TILE);
@@ -187,11 +232,18 @@ __device__ __forceinline__ void shoot_patch(const ShootArgs &a, int64_t patch, S
                                               by);
         __syncthreads();
 
-        // Whole groups in the loop; the last tile may end with half a group, summed
-        // after it (code of its own, so the loop's schedule is that of whole groups).
+        // Whole groups of real lenses with four-ray reciprocals where the tile's lenses
+        // and the patch allow them; then the rest (groups holding padding lenses, at
+        // offset PAD_OFFSET, or every group of a tile out of range) with two-ray ones. The
+        // last tile may end with half a group, summed by code of its own, so that the
+        // loops' schedules are those of whole groups.
+        const int tile_idx = (int)(t0 / LENS_TILE);
+        const int full_q = (quad_patch && sm.far_tile != tile_idx) ? cnt / GROUP * GROUP : 0;
         const int full = cnt_pad / GROUP * GROUP;
-        for (int g = 0; g < full; g += GROUP) group_sums<GROUP, RX, RY, UNIT>(tile, g, rxl, ryl, Ax, Ay);
-        if (full < cnt_pad) group_sums<GROUP / 2, RX, RY, UNIT>(tile, full, rxl, ryl, Ax, Ay);
+        int g = 0;
+        for (; g < full_q; g += GROUP) group_sums<GROUP, RX, RY, UNIT, true, CQ>(tile, g, rxl, ryl, Ax, Ay);
+        for (; g < full; g += GROUP) group_sums<GROUP, RX, RY, UNIT, false, CQ>(tile, g, rxl, ryl, Ax, Ay);
+        if (full < cnt_pad) group_sums<GROUP / 2, RX, RY, UNIT, false, CQ>(tile, full, rxl, ryl, Ax, Ay);
     }
 
     // Block-wide error bound (mixed mode).
@@ -238,8 +290,10 @@ __device__ __forceinline__ void shoot_patch(const ShootArgs &a, int64_t patch, S
             const double y2 = a.c2 * x2 - Ay[r][c];
             const double u = (y1 - a.tx0) * a.inv_pixw;
             const double v = (y2 - a.ty0) * a.inv_pixh;
+            const int cp = ((c / CQ) % 2) ? c - CQ : c + CQ;   // the column partner of the four-ray reciprocal
             int code = classify_ray<MODE>(a, x1, x2, Ax[r][c], Ay[r][c], u, v, rxl[c], ryl[r], rxl[c], ryl[r ^ 1],
-                                          Bx, By, n_near, all_flagged, sm.near_list, k_term, h_f, tiny_r2);
+                                          rxl[cp], quad_patch, Bx, By, n_near, all_flagged, sm.near_list, k_term,
+                                          h_f, tiny_r2);
             if (!valid) code = INT32_MIN;
 
             n_in += __builtin_popcountll(__ballot(code >= 0));

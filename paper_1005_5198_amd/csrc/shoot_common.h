@@ -22,6 +22,22 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
 // add 2u.
 constexpr double K_TERM_UNIT = 12.5;
 constexpr double K_TERM_MASS = 15.0;
+// Regular-grid unit-mass loop: one reciprocal for four rays (two rows of two
+// columns) through the product of their r^2; b * (rcp(P) * cd) with
+// P = (a b)(c d) is within 6u of 1/a (three products, the reciprocal, two
+// multiplies; the rounding of c d cancels), so the term constant grows by 2.
+constexpr double K_TERM_QUAD = 14.5;
+constexpr double K_TERM_MASS_QUAD = 17.0;   // the same with masses (+2u)
+// Range of the four-ray product P = r_a^2 r_b^2 r_c^2 r_d^2 in FP32: a tile whose
+// lenses all lie within QUAD_RANGE of the patch centre on both axes, in a patch
+// of half-diagonal h in [QUAD_H_MIN, QUAD_H_MAX], keeps P below 2^110 (no
+// overflow); lenses outside the near list are at least 2h from every ray, so P
+// stays above 256 h^8 >= 2^-100 (normal, with room); near lenses are checked per
+// ray. Other tiles and patches use the two-ray form.
+constexpr double QUAD_RANGE = 8192.0;
+constexpr double QUAD_H_MIN = 1.0e-4;
+constexpr double QUAD_H_MAX = 1024.0;
+constexpr double QUAD_P_MIN = 7.888609052210118e-31;   // 2^-100
 constexpr double K_GROUP = 1.01;
 constexpr double K_H = 6.5;
 
@@ -60,6 +76,7 @@ struct ShootSmem {
     float4 tile[LENS_TILE];        // UNIT: two (x,y) pairs per float4; else (x,y,m,0)
     NearLens near_list[NEAR_MAX];
     int near_count;
+    int far_tile;                  // last tile (index) with a lens beyond QUAD_RANGE of the patch centre
     double red_bx[16], red_by[16];
 };
 
@@ -117,6 +134,8 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
                 fx = (float)Lx;
                 fy = (float)Ly;
                 fm = (float)m;
+                // (every thread that finds one writes the same value)
+                if (!(fmax(fabs(Lx), fabs(Ly)) <= QUAD_RANGE)) sm.far_tile = (int)(t0 / LENS_TILE);
                 if (MODE == 1) {
                     const double alx = fabs(Lx), aly = fabs(Ly);
                     const double ex = fmax(alx - hx, 0.0), ey = fmax(aly - hy, 0.0);
@@ -156,12 +175,15 @@ __device__ __forceinline__ void stage_tile(const ShootArgs &a, int64_t t0, int c
 // bound is the block's (Bx, By) plus the near lenses' per-ray terms, and a ray
 // within it of a pixel edge is FLAGGED for the FP64 re-check. (rxp, ryp) is the
 // ray whose reciprocals this one's share: a near lens almost on either of the
-// two flags it (their product of r^2 could underflow); a ray with a non-finite
-// position is never counted out, only flagged.
+// two flags it (their product of r^2 could underflow). With quad set, the ray
+// also shares reciprocals with the two rays of column rxq (rows ry and ryp), and
+// a near lens whose four r^2, or either pair of them, multiply to less than
+// QUAD_P_MIN flags it too. A ray with a non-finite position is never counted
+// out, only flagged.
 template <int MODE>
 __device__ __forceinline__ int classify_ray(const ShootArgs &a, double x1, double x2, double Axv, double Ayv, double u,
-                                            double v, float rx, float ry, float rxp, float ryp, double Bx,
-                                            double By, int n_near,
+                                            double v, float rx, float ry, float rxp, float ryp, float rxq, bool quad,
+                                            double Bx, double By, int n_near,
                                             bool all_flagged, const NearLens *near_list, double k_term, float h_f,
                                             float tiny_r2) {
     int code;
@@ -180,7 +202,14 @@ __device__ __forceinline__ int classify_ray(const ShootArgs &a, double x1, doubl
             const float dxp = rxp - nl.x, dyp = ryp - nl.y;
             const float r2p = dxp * dxp + dyp * dyp;
             const float wgt = (float)(k_term + K_GROUP * (double)(GROUP - nl.pos));
-            if (!(r2n > tiny_r2) || !(r2p > tiny_r2)) {
+            bool quad_ok = true;
+            if (quad) {
+                const float dxq = rxq - nl.x;
+                const double r2q = (double)(dxq * dxq + dyn * dyn), r2qp = (double)(dxq * dxq + dyp * dyp);
+                const double pa = (double)r2n * (double)r2p, pc = r2q * r2qp;
+                quad_ok = pa > QUAD_P_MIN && pc > QUAD_P_MIN && pa * pc > QUAD_P_MIN;
+            }
+            if (!(r2n > tiny_r2) || !(r2p > tiny_r2) || !quad_ok) {
                 cx = __builtin_inff();
                 cy = __builtin_inff();
             } else {

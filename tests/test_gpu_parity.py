@@ -192,9 +192,24 @@ def test_edge_cases(rs, case):
 
 
 def test_shared_reciprocal_range_guards(rs):
-    """The FP32 loop shares one reciprocal between two rows through the product of their r^2.
-    A lens beyond 1e9 (the product could overflow) flags every block, and a patch under 1e-6
-    across (the product could underflow) is flagged whole: both maps still equal the oracle's."""
+    """The FP32 loop shares one reciprocal between four rays (or two, outside the four-ray
+    range) through the product of their r^2. A lens beyond 1e9 (a product of two could
+    overflow) flags every block, and a patch under 1e-6 across (it could underflow) is
+    flagged whole; a tile with a lens beyond 8192 of a patch, or a patch under 1e-4 across,
+    sums with two-ray reciprocals instead. Every map still equals the oracle's, in both the
+    mixed and the FP32 mode."""
+    rng0 = np.random.default_rng(37)
+    # one far lens (beyond the four-ray range, well inside 1e9) in the first tile of 2000
+    lens = np.concatenate([[[3.0e5, -2.0e5]], rng0.uniform(-9, 9, size=(1999, 2))])
+    p = w.make_params(0.3, 0.1, 0.2, (-6.0, -5.0, 12.0, 10.0, 300, 200), (-4.0, -4.0, 8.0, 8.0, 40, 40))
+    spec = w.MapSpec("lens_beyond_quad_range", p, lens, None)
+    check_mixed_exact(rs, spec)
+    check_pixels(rs, spec, fp32_budget=1e-4)
+    # patches 64 x 32 rays of 1e-6 x 1e-6: half-diagonal about 4e-5, two-ray path, not flagged
+    small = w.make_params(0.3, 0.0, 0.1, (0.25, 0.5, 1.28e-4, 6.4e-5, 128, 64), (-100.0, -100.0, 200.0, 200.0, 64, 64))
+    spec = w.MapSpec("small_patch", small, rng0.uniform(-3, 3, size=(25, 2)), None)
+    st = check_mixed_exact(rs, spec)
+    assert st["rays_rechecked"] < 128 * 64
     rng = np.random.default_rng(31)
     lens = np.concatenate([rng.uniform(-9, 9, size=(40, 2)), [[2.0e9, 1.0]]])
     p = w.make_params(0.3, 0.1, 0.2, (-6.0, -5.0, 12.0, 10.0, 160, 96), (-4.0, -4.0, 8.0, 8.0, 40, 40))
