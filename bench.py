@@ -60,8 +60,8 @@ def parse():
                     help="skip the plain-FP32 mode's changed-ray fraction and map error on the config-2 map")
     ap.add_argument("--no-other-maps", action="store_true",
                     help="skip the 32768^2-ray map and the paper's sigma=0.4 point (each mode)")
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-rho", type=float, default=0.8)
+    ap.add_argument("--serve-requests", type=int, default=96,
+                    help="requests per request-loop leg (load 0.8, 1.2, and 0.8 with an 8 MiB pool)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales HBM byte counters)")
     return ap.parse_args()
@@ -215,8 +215,7 @@ def main():
         if not args.no_batched:
             result["batched"] = bench_extra.batched(rs, mode=args.mode)
         if not args.no_serve:
-            result["served"] = bench_extra.served(rs, n_requests=args.serve_requests, rho=args.serve_rho,
-                                                  mode=args.mode)
+            result["served"] = bench_extra.served_legs(rs, n_requests=args.serve_requests, mode=args.mode)
         if not args.no_stats:
             result["map_stats"] = bench_extra.map_stats(rs)
         if not args.no_farfield:

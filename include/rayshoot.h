@@ -78,8 +78,7 @@ extern "C" {
 #define RS_EINVAL (-1)     /* bad argument (sizes, extents, window, null pointer, mode) */
 #define RS_ENOMEM (-2)     /* workspace too small, or server budget cannot hold a request */
 #define RS_EHIP (-3)       /* a HIP runtime call failed */
-#define RS_EBUSY (-4)      /* reserved for a full server queue; not returned: rs_server_submit
-                              never blocks and its waiting queue has no bound */
+#define RS_EBUSY (-4)      /* the server's waiting queue is full (rs_server_submit never blocks) */
 #define RS_ECANCELED (-5)  /* request cancelled */
 
 #define RS_FP32 0
@@ -308,6 +307,8 @@ typedef struct {
     double slice_ms;          /* target GPU time of one launch step; <= 0 selects 10 ms; four
                                  times that while requests wait for admission */
     double starve_s;          /* a request older than this is served first; <= 0 selects 0.5 s */
+    int32_t max_waiting;      /* requests waiting for admission before rs_server_submit returns
+                                 RS_EBUSY; <= 0 selects 4096 */
 } rs_server_cfg;
 
 typedef struct {
@@ -320,20 +321,23 @@ typedef struct {
     double maps_per_s;                     /* completed / (last completion - first submission) */
     double latency_p50_s, latency_p99_s;   /* submission -> map in host memory, completed requests */
     double latency_mean_s, latency_max_s;
+    uint64_t rejected_busy;                /* submissions refused with RS_EBUSY */
 } rs_server_stats;
 
 typedef struct rs_server rs_server;
 
-/* Start a server on the current device: allocates its pool and four streams (two for launch
-   steps, one for admission, one for copies back), starts its thread. */
+/* Start a server on the current device: allocates its pool, four streams (two for launch
+   steps, one for admission, one for copies back) and pinned host buffers for the step
+   counters, starts its thread. */
 int rs_server_create(const rs_server_cfg *cfg, rs_server **server);
 
 /*
  * Queue one map. The parameters and the HOST lens arrays are copied before the
  * call returns; map_host (HOST, uint32 [npy][npx], or NULL to discard) must stay
  * valid until rs_server_wait returns for the ticket. The window must hold fewer
- * than 2^32 rays. Errors: RS_EINVAL, RS_ECANCELED (server stopping), RS_EHIP
- * (the server has stopped after a device error or found no device).
+ * than 2^32 rays. Errors: RS_EINVAL, RS_EBUSY (cfg.max_waiting requests are already
+ * waiting for admission; nothing is queued, try again later), RS_ECANCELED (server
+ * stopping), RS_EHIP (the server has stopped after a device error or found no device).
  */
 int rs_server_submit(rs_server *server, const rs_map_params *params, const double *lens_xy_host,
                      const double *lens_m_host, int64_t n_lens, uint32_t *map_host, uint64_t *ticket);

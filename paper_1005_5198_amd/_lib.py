@@ -64,14 +64,16 @@ class MapRequest(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("slice_ms", ctypes.c_double), ("starve_s", ctypes.c_double)]
+                ("mode", ctypes.c_int32), ("slice_ms", ctypes.c_double), ("starve_s", ctypes.c_double),
+                ("max_waiting", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("completed", "canceled", "failed", "steps", "waiting", "active",
                                                "max_waiting", "hbm_in_use_bytes", "hbm_peak_bytes")] + \
                [(n, ctypes.c_double) for n in ("interactions", "gpu_busy_s", "maps_per_s", "latency_p50_s",
-                                               "latency_p99_s", "latency_mean_s", "latency_max_s")]
+                                               "latency_p99_s", "latency_mean_s", "latency_max_s")] + \
+               [("rejected_busy", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: (int(v) if isinstance(v, int) else float(v)) for k, v in

@@ -293,9 +293,11 @@ class Server:
     """The request loop (continuous batching). Inputs are host arrays; results come back as numpy maps."""
 
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_inflight: int = 16, mode: str = "mixed",
-                 slice_ms: float = 10.0, starve_s: float = 0.5):
+                 slice_ms: float = 10.0, starve_s: float = 0.5, max_waiting: int = 0):
+        """max_waiting: requests waiting for admission before submit raises RS_EBUSY (0: 4096)."""
         _device()
-        cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms), float(starve_s))
+        cfg = L.ServerCfg(int(hbm_budget_bytes), int(max_inflight), MODES[mode], float(slice_ms), float(starve_s),
+                          int(max_waiting))
         h = ctypes.c_void_p()
         L.check(L.lib().rs_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -120,13 +120,22 @@ def served(rs, n_requests: int = 48, rho: float = 0.8, mode: str = "mixed", seed
     p50p, p99p = _percentiles(lat_plain)
     inter = sum(s.interactions for s in specs)
     return {"workload": f"config4: {n_requests} Poisson requests at rho={rho} of the one-at-a-time rate "
-                        f"({rate:.2f}/s), config-3 distribution, {mode} mode",
-            "requests": n_requests, "arrival_rate_per_s": rate, "interactions": inter,
+                        f"({rate:.2f}/s), config-3 distribution, {mode} mode, device pool {budget_bytes >> 20} MiB",
+            "requests": n_requests, "rho": rho, "arrival_rate_per_s": rate, "interactions": inter,
+            "hbm_budget_bytes": budget_bytes,
             "served_maps_per_s": st["maps_per_s"], "served_p50_s": st["latency_p50_s"],
             "served_p99_s": st["latency_p99_s"], "served_span_s": span_served, "served_steps": st["steps"],
             "served_max_waiting": st["max_waiting"], "served_hbm_peak_bytes": st["hbm_peak_bytes"],
             "plain_maps_per_s": n_requests / span_plain, "plain_p50_s": p50p, "plain_p99_s": p99p,
             "plain_span_s": span_plain, "identical_first8": identical}
+
+
+def served_legs(rs, n_requests: int = 96, mode: str = "mixed") -> dict:
+    """The request loop at load 0.8 and 1.2 of the one-at-a-time rate, and at 0.8 with a
+    device pool of 8 MiB, small enough that admission by footprint makes requests wait."""
+    return {"rho_0.8": served(rs, n_requests=n_requests, rho=0.8, mode=mode),
+            "rho_1.2": served(rs, n_requests=n_requests, rho=1.2, mode=mode),
+            "rho_0.8_budget_8MiB": served(rs, n_requests=n_requests, rho=0.8, mode=mode, budget_bytes=8 << 20)}
 
 
 def map_stats(rs, side: int = 4096, n_rays_a: float = 500.0, n_rays_b: float = 1000.0, reps: int = 20) -> dict:

@@ -1,0 +1,45 @@
+// Sizes and workspace layout of the library's launches: plain constants, shared
+// by the HIP kernels, the host runtime and the host-only planning code.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rs {
+
+// Ray patch of one block of the deflection kernel: PATCH_X x PATCH_Y rays,
+// lanes laid out 8 x 8 per wave. The thread shape (rays per lane, waves per
+// block) is a tunable choice among N_SHAPES that all cover the same patch.
+constexpr int LANES_X = 8;
+constexpr int LANES_Y = 8;
+constexpr int PATCH_X = 64;
+constexpr int PATCH_Y = 32;
+constexpr int N_SHAPES = 4;
+
+// Lenses staged into LDS per tile, and lenses per FP32 partial sum before it
+// is folded into the FP64 accumulator.
+constexpr int LENS_TILE = 1024;
+constexpr int GROUP = 32;
+constexpr int NEAR_MAX = 64;                  // per-block list of lenses close to the patch
+
+// Workspace layout (bytes).
+constexpr size_t WS_COUNTERS = 0;             // uint64 [8]: in, out, singular, rechecked, spare
+constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] each: queue lengths, live counts, unresolved counts
+constexpr int64_t CHUNK_RAYS = int64_t(1) << 27;  // rays per launch (queue capacity)
+
+enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3, C_DIRECT = 4 };
+constexpr int N_COUNTERS = 8;
+
+constexpr int FF_SP_X = 4;
+constexpr int FF_SP_Y = 4;
+constexpr int FF_NEAR_CAP = 4096;    // single maps (the far-field mode rescans all lenses beyond it)
+constexpr int FF_BATCH_CAP = 1024;   // batches (the re-check stage only; beyond it, the stage over every lens)
+constexpr int FF_REC_DOUBLES = 36;
+
+// Random rays: expected rays per bin (a block's capacity is 2048, so a bin
+// overflows it only beyond three standard deviations, about one bin in 3000,
+// and then takes a second pass), and the largest launch.
+constexpr int64_t RAND_BIN_RAYS = 1900;
+constexpr int64_t RAND_CHUNK_RAYS = int64_t(1) << 26;
+
+}  // namespace rs

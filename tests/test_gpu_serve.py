@@ -88,3 +88,27 @@ def test_cancel_and_oversize(rs):
         assert e.value.code == RS_ENOMEM
         st = srv.stats()
     assert st["canceled"] == 1 and st["failed"] == 1 and st["completed"] == 2
+
+
+def test_full_queue_refuses_with_ebusy(rs):
+    """One slot, a waiting queue of two: a burst of submissions behind a long request is
+    refused with RS_EBUSY beyond the queue; the accepted ones equal maps made alone."""
+    from paper_1005_5198_amd._lib import RayshootError, RS_EBUSY
+    long_one = w.config2().window(0, 19200, 0, 640)        # ~2e11 interactions, tens of ms
+    small = small_requests(6, seed=43)
+    with rs.Server(hbm_budget_bytes=256 << 20, max_inflight=1, mode="mixed", slice_ms=5.0, max_waiting=2) as srv:
+        accepted = [(long_one, srv.submit(long_one.params, long_one.lens_xy))]
+        refused = 0
+        for s in small:
+            try:
+                accepted.append((s, srv.submit(s.params, s.lens_xy)))
+            except RayshootError as e:
+                assert e.code == RS_EBUSY
+                refused += 1
+        maps = [(s, srv.wait(t)[0]) for s, t in accepted]
+        st = srv.stats()
+    say("ebusy stats", st, "refused", refused)
+    assert refused >= 1 and st["rejected_busy"] == refused
+    assert st["completed"] == len(accepted)
+    for s, m in maps:
+        assert np.array_equal(m, rs.make_map(s.params, s.lens_xy, mode="mixed").cpu().numpy()), s.name
