@@ -39,7 +39,7 @@ METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batch
 # HBM bytes per launch of the mixed-mode deflection kernel on this workload: rocprofv3 --pmc
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB copy), measured on the current
 # kernel (profiles/shoot_kernel_config2.md). Set to None whenever the kernel changes.
-TRAFFIC_BYTES_PER_LAUNCH = None
+TRAFFIC_BYTES_PER_LAUNCH = 1.476e9
 
 
 def parse():
