@@ -28,6 +28,19 @@ constexpr int FAR_THREADS = 256;
 constexpr int FAR_ROWS = PATCH_X * PATCH_Y / FAR_THREADS;     // rays per thread (8)
 static_assert(FAR_ROWS * (FAR_THREADS / 64) == (PATCH_X / 8) * (PATCH_Y / 8), "8 x 8 blocks cover the patch");
 constexpr int NEAR_EXP = 512;
+
+// binom(n, m) for n, m < FAR_P (Pascal's triangle; integers below 2^13, exact in FP64).
+struct BinomTable {
+    double v[FAR_P][FAR_P];
+    constexpr BinomTable() : v() {
+        for (int n = 0; n < FAR_P; ++n) {
+            v[n][0] = 1.0;
+            for (int m = 1; m <= n; ++m) v[n][m] = v[n - 1][m - 1] + (m < n ? v[n - 1][m] : 0.0);
+        }
+    }
+};
+__constant__ constexpr BinomTable BINOM_TABLE{};
+#define BINOM BINOM_TABLE.v
 // One lens's contribution to an expansion about (ox, oy) with half-diagonal h
 // (the lens is at least FAR_RATIO h away): the powers m t^(n+1) and the bound
 // terms m/|d|, m/|d| rho^P / (1 - rho) and sqrt(2) m / (|d| - h).
@@ -194,6 +207,7 @@ __global__ __launch_bounds__(FAR_THREADS) void batch_super_kernel(const BatchArg
 }
 
 struct FarSmem {
+    PixelTable table;            // the patch's counts per pixel (map mode)
     double near_x[NEAR_EXP], near_y[NEAR_EXP], near_m[NEAR_EXP];
     int near_count;
     double part[FAR_THREADS / 64][FAR_REC];
@@ -250,6 +264,7 @@ __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArg
     const bool scan_all = listed > a.ff_cap;
     if (tid == 0) sm.near_count = 0;
     if (tid < FAR_REC) sm.sc[tid] = a.ff_super[sp * (int64_t)FAR_REC + tid];
+    if (!PIX) table_clear<FAR_THREADS>(sm.table, tid);
     __syncthreads();
 
     // The super-patch's nearer lenses: far from this patch -> its own expansion; else direct.
@@ -280,14 +295,13 @@ __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArg
         const double e1 = cx - ox, e2 = cy - oy;
         double s1 = 0.0, s2 = 0.0;
         double g1 = 1.0, g2 = 0.0;   // e^(n-m)
-        double binom = 1.0;          // binom(n, m), exact in FP64 for n < 16
         for (int n = mm; n < FAR_P; ++n) {
+            const double binom = BINOM[n][mm];   // exact in FP64 for n < 16
             s1 = __builtin_fma(binom, g1 * sm.sc[n] - g2 * sm.sc[FAR_P + n], s1);
             s2 = __builtin_fma(binom, g1 * sm.sc[FAR_P + n] + g2 * sm.sc[n], s2);
             const double q1 = g1 * e1 - g2 * e2, q2 = g1 * e2 + g2 * e1;
             g1 = q1;
             g2 = q2;
-            binom = binom * (double)(n + 1) / (double)(n + 1 - mm);
         }
         sm.tc[mm] = s1 + sm.pc[mm];
         sm.tc[FAR_P + mm] = s2 + sm.pc[FAR_P + mm];
@@ -309,57 +323,90 @@ __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArg
 
     unsigned long long n_in = 0, n_out = 0;
     const int64_t W = a.i1 - a.i0;
-    // the coefficients stay in registers for every ray of this thread
-    double T1[FAR_P], T2[FAR_P];
-#pragma unroll
-    for (int n = 0; n < FAR_P; ++n) {
-        T1[n] = sm.tc[n];
-        T2[n] = sm.tc[FAR_P + n];
-    }
     // A wave takes 8 x 8-ray blocks of the patch (block wave + 4 r, r < 8), so the
-    // rays of one wave land on few pixels and the binning atomics aggregate well.
+    // rays of one wave land on few pixels. Ray r of this thread has column
+    // ib + 8 ((wave + 4 r) % 8) + lane % 8 (two values, r even or odd) and row
+    // jb + 8 (r / 2) + lane / 8 (four values).
     const int wave = tid >> 6;
-#pragma unroll 2
-    for (int r = 0; r < FAR_ROWS; ++r) {
-        const int b = wave + (FAR_THREADS / 64) * r;
-        const int64_t i = ib + 8 * (b % (PATCH_X / 8)) + (lane & 7);
-        const int64_t j = jb + 8 * (b / (PATCH_X / 8)) + (lane >> 3);
-        const bool valid = (i < a.i1) && (j < a.jc1);
-        const double x1 = ray_coord(a.sx0, i, a.spx);
-        const double x2 = ray_coord(a.sy0, j, a.spy);
-        const double nw1 = ox - x1, nw2 = oy - x2;   // -w
-        double S1 = T1[FAR_P - 1], S2 = T2[FAR_P - 1];
+    auto col = [&](int c) { return ib + 8 * ((wave + 4 * c) % (PATCH_X / 8)) + (lane & 7); };
+    auto row = [&](int rr) { return jb + 8 * rr + (lane >> 3); };
+    double X1[2], X2[FAR_ROWS / 2];
 #pragma unroll
-        for (int n = FAR_P - 2; n >= 0; --n) {
-            const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, T1[n]));
-            const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, T2[n]));
-            S1 = q1;
-            S2 = q2;
+    for (int c = 0; c < 2; ++c) X1[c] = ray_coord(a.sx0, col(c), a.spx);
+#pragma unroll
+    for (int rr = 0; rr < FAR_ROWS / 2; ++rr) X2[rr] = ray_coord(a.sy0, row(rr), a.spy);
+    // The thread's rays in two passes of RPASS: per pass, (1) the expansion of each
+    // ray (independent Horner chains), (2) the near lenses, each read from LDS once
+    // per pass and added onto each ray's far part in list order, (3) the pixel
+    // decision and binning into the block's pixel table.
+    constexpr int RPASS = FAR_ROWS / 2;
+#pragma unroll
+    for (int pass = 0; pass < FAR_ROWS / RPASS; ++pass) {
+        double A1[RPASS], A2[RPASS];
+        {
+            double T1[FAR_P], T2[FAR_P];
+#pragma unroll
+            for (int n = 0; n < FAR_P; ++n) {
+                T1[n] = sm.tc[n];
+                T2[n] = sm.tc[FAR_P + n];
+            }
+#pragma unroll
+            for (int k = 0; k < RPASS; ++k) {
+                const int r = pass * RPASS + k;
+                const double nw1 = ox - X1[r & 1], nw2 = oy - X2[r >> 1];   // -w
+                double S1 = T1[FAR_P - 1], S2 = T2[FAR_P - 1];
+#pragma unroll
+                for (int n = FAR_P - 2; n >= 0; --n) {
+                    const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, T1[n]));
+                    const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, T2[n]));
+                    S1 = q1;
+                    S2 = q2;
+                }
+                A1[k] = S1;
+                A2[k] = -S2;
+            }
         }
-        double a1 = S1, a2 = -S2;
-        double snear = 0.0;
-        bool tiny = false;
+        double SN[RPASS];
+#pragma unroll
+        for (int k = 0; k < RPASS; ++k) SN[k] = 0.0;
+        uint32_t tiny = 0u;
         for (int q = 0; q < n_near; ++q) {
-            const double e1 = x1 - sm.near_x[q], e2 = x2 - sm.near_y[q];
-            const double r2 = __builtin_fma(e1, e1, e2 * e2);
-            tiny |= !(r2 > 1e-200);
-            const double f = sm.near_m[q] * rcp64(r2);
-            a1 = __builtin_fma(f, e1, a1);
-            a2 = __builtin_fma(f, e2, a2);
-            snear = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), snear);
+            const double X = sm.near_x[q], Y = sm.near_y[q], M = sm.near_m[q];
+#pragma unroll
+            for (int k = 0; k < RPASS; ++k) {
+                const int r = pass * RPASS + k;
+                const double e1 = X1[r & 1] - X, e2 = X2[r >> 1] - Y;
+                const double r2 = __builtin_fma(e1, e1, e2 * e2);
+                if (!(r2 > 1e-200)) tiny |= 1u << k;
+                const double f = M * rcp64(r2);
+                A1[k] = __builtin_fma(f, e1, A1[k]);
+                A2[k] = __builtin_fma(f, e2, A2[k]);
+                SN[k] = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), SN[k]);
+            }
         }
-        int code = far_decide(a, x1, x2, a1, a2, far_err, SFAR, SDEF, snear, n_near, !tiny && !all_flagged);
-        if (!valid) code = INT32_MIN;
+#pragma unroll
+        for (int k = 0; k < RPASS; ++k) {
+            const int r = pass * RPASS + k;
+            const int64_t i = col(r & 1), j = row(r >> 1);
+            const bool valid = (i < a.i1) && (j < a.jc1);
+            int code = far_decide(a, X1[r & 1], X2[r >> 1], A1[k], A2[k], far_err, SFAR, SDEF, SN[k], n_near,
+                                  !((tiny >> k) & 1u) && !all_flagged);
+            if (!valid) code = INT32_MIN;
 
-        n_in += __builtin_popcountll(__ballot(code >= 0));
-        n_out += __builtin_popcountll(__ballot(code == OUT));
-        if (PIX) {
-            if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-        } else {
-            aggregated_add(a.map, code);
+            n_in += __builtin_popcountll(__ballot(code >= 0));
+            n_out += __builtin_popcountll(__ballot(code == OUT));
+            if (PIX) {
+                if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+            } else {
+                table_add(sm.table, a.map, code);
+            }
+            const uint64_t fl = __ballot(code == FLAGGED);
+            if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
         }
-        const uint64_t fl = __ballot(code == FLAGGED);
-        if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
+    }
+    if (!PIX) {
+        __syncthreads();   // every ray of the patch is in the table
+        table_flush<FAR_THREADS>(sm.table, a.map, tid);
     }
     if (lane == 0) {
         if (n_in) atomicAdd(a.counters + C_IN, n_in);

@@ -72,6 +72,51 @@ __device__ __forceinline__ void aggregated_add(uint32_t *map, int p) {
     }
 }
 
+// A block's counts per pixel in LDS (open addressing on the pixel index): rays add
+// with LDS atomics, and the block then adds each distinct pixel's count to the map
+// with one global atomic. A ray whose pixel finds no free slot within PT_PROBES
+// probes adds to the map directly. Counts are integers, so the map does not depend
+// on the order of the additions.
+constexpr int PT_SLOTS = 2048;
+constexpr int PT_PROBES = 8;
+struct PixelTable {
+    uint32_t key[PT_SLOTS];   // pixel + 1; 0 = empty
+    uint32_t cnt[PT_SLOTS];
+};
+
+template <int THREADS>
+__device__ __forceinline__ void table_clear(PixelTable &t, int tid) {
+    for (int s = tid; s < PT_SLOTS; s += THREADS) {
+        t.key[s] = 0u;
+        t.cnt[s] = 0u;
+    }
+}
+
+// Count one ray in pixel p (p < 0: nothing to count).
+__device__ __forceinline__ void table_add(PixelTable &t, uint32_t *map, int p) {
+    if (p < 0) return;
+    const uint32_t k = (uint32_t)p + 1u;
+    uint32_t s = (k * 2654435761u) >> 21;   // multiplicative hash onto 2^11 slots
+    for (int probe = 0; probe < PT_PROBES; ++probe) {
+        const uint32_t old = atomicCAS(&t.key[s], 0u, k);
+        if (old == 0u || old == k) {
+            atomicAdd(&t.cnt[s], 1u);
+            return;
+        }
+        s = (s + 1u) & (PT_SLOTS - 1);
+    }
+    atomicAdd(map + p, 1u);
+}
+static_assert(PT_SLOTS == 1 << 11, "the hash keeps 11 bits");
+
+template <int THREADS>
+__device__ __forceinline__ void table_flush(const PixelTable &t, uint32_t *map, int tid) {
+    for (int s = tid; s < PT_SLOTS; s += THREADS) {
+        const uint32_t c = t.cnt[s];
+        if (c) atomicAdd(map + (t.key[s] - 1u), c);
+    }
+}
+
 struct ShootSmem {
     float4 tile[LENS_TILE];        // UNIT: two (x,y) pairs per float4; else (x,y,m,0)
     NearLens near_list[NEAR_MAX];
