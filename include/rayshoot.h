@@ -201,6 +201,10 @@ int rs_make_map_noalloc(const rs_map_params *params, const double *lens_xy, cons
  * events and returns the summed kernel milliseconds, the number of launches
  * and the ray-lens interactions those launches covered, then resets the sums.
  * Used by the benchmark's roofline figure.
+ * Two further aids need no call: the environment variable RAYSHOOT_DEBUG=1 makes
+ * the library print each map's launch plan and each batch's choice to stderr (=2
+ * also the request loop's steps), and named roctx ranges mark its phases for
+ * rocprofv3 --marker-trace.
  */
 int rs_profile_enable(int on);
 int rs_profile_read(double *kernel_ms, int64_t *launches, double *interactions);
@@ -228,9 +232,12 @@ typedef struct {
  * Time every shape on a sample of this map (a band of rows from the middle of
  * the window holding about sample_rays rays; <= 0 picks 2^22) and remember the
  * fastest for maps with the same signature (mode, unit or general masses,
- * N* rounded to a power of two). Later rs_make_map calls with that signature
- * use it. scratch_map (device, uint32 [npy][npx]) is overwritten. Synchronises
- * the stream. Errors as rs_make_map.
+ * N* rounded down to a power of two, the window's 64 x 32-ray patches rounded
+ * down to a power of two). Later rs_make_map calls with that signature use it.
+ * scratch_map (device, uint32 [npy][npx]) is overwritten. Synchronises the
+ * stream. When the environment variable RAYSHOOT_TUNE_CACHE names a file, the
+ * cache is loaded from it on first use and written to it after every tuning run.
+ * Errors as rs_make_map.
  */
 int rs_tune(const rs_map_params *params, const double *lens_xy, const double *lens_m, int64_t n_lens,
             uint32_t *scratch_map, void *workspace, size_t workspace_bytes, int64_t sample_rays,
@@ -243,7 +250,9 @@ int rs_tune(const rs_map_params *params, const double *lens_xy, const double *le
  */
 int rs_set_shape(int shape, int *previous);
 
-/* Write / read the tuner's cache as text (one "mode unit n_bucket shape" line each). */
+/* Write / read the tuner's cache as text, one line per entry:
+   "kind mode unit n_bucket patch_bucket choice" (kind 0: single maps, choice = shape;
+   kind 1: batches, choice = shape + 16 * blocks per CU, 0 blocks = as many as fit). */
 int rs_tune_save(const char *path);
 int rs_tune_load(const char *path);
 
@@ -281,6 +290,31 @@ size_t rs_batch_workspace_bytes(const rs_map_request *requests, int32_t n);
  */
 int rs_make_maps(const rs_map_request *requests, int32_t n, void *workspace, size_t workspace_bytes,
                  void *stream);
+
+#define RS_MAX_BATCH_CHOICES 16
+
+typedef struct {
+    int32_t best;                                 /* index of the fastest candidate */
+    int32_t n;                                    /* candidates timed */
+    int32_t shape[RS_MAX_BATCH_CHOICES];          /* thread shape of each candidate */
+    int32_t blocks_per_cu[RS_MAX_BATCH_CHOICES];  /* persistent blocks per CU (0 = as many as fit) */
+    double ms[RS_MAX_BATCH_CHOICES];              /* persistent deflection launch on the sample, ms */
+    double sample_interactions;                   /* ray-lens interactions in the sample */
+} rs_tune_batch_result;
+
+/*
+ * Autotune a batch: time the persistent deflection launch for every thread shape
+ * and persistent grid (all blocks that fit per CU, 3, 2) on a sample made of a
+ * band of whole patch rows (about sample_rays rays; <= 0 picks 2^20) from the
+ * middle of every map's window, and remember the fastest for batches with the
+ * same signature (mode, unit or general masses, the heaviest map's N* and the
+ * batch's patch count, each rounded down to a power of two; RAYSHOOT_TUNE_CACHE
+ * as for rs_tune). The requests' maps are overwritten (scratch); the workspace
+ * needs rs_batch_workspace_bytes of the requests. Synchronises the stream.
+ * Errors as rs_make_maps.
+ */
+int rs_tune_batch(const rs_map_request *requests, int32_t n, void *workspace, size_t workspace_bytes,
+                  int64_t sample_rays, void *stream, rs_tune_batch_result *result_host);
 
 /* Counters of each map of the last rs_make_maps on this workspace, in request order. Synchronises. */
 int rs_batch_read_stats(const void *workspace, int32_t n, rs_map_stats *stats_host, void *stream);

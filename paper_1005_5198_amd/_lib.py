@@ -86,6 +86,12 @@ class TuneResult(ctypes.Structure):
                 ("ms", ctypes.c_double * 8), ("sample_interactions", ctypes.c_double)]
 
 
+class TuneBatchResult(ctypes.Structure):
+    _fields_ = [("best", ctypes.c_int32), ("n", ctypes.c_int32), ("shape", ctypes.c_int32 * 16),
+                ("blocks_per_cu", ctypes.c_int32 * 16), ("ms", ctypes.c_double * 16),
+                ("sample_interactions", ctypes.c_double)]
+
+
 class CompareResult(ctypes.Structure):
     _fields_ = [("rms_dm", ctypes.c_double), ("ks_d", ctypes.c_double), ("ks_p", ctypes.c_double),
                 ("mean_mu_a", ctypes.c_double), ("mean_mu_b", ctypes.c_double),
@@ -124,6 +130,7 @@ def _declare(lib):
         "rs_batch_workspace_bytes": ([P(MapRequest), ctypes.c_int32], SZ),
         "rs_make_maps": ([P(MapRequest), ctypes.c_int32, VP, SZ, VP], INT),
         "rs_batch_read_stats": ([VP, ctypes.c_int32, P(MapStats), VP], INT),
+        "rs_tune_batch": ([P(MapRequest), ctypes.c_int32, VP, SZ, I64, VP, P(TuneBatchResult)], INT),
         "rs_server_create": ([P(ServerCfg), P(VP)], INT),
         "rs_server_submit": ([VP, P(MapParams), VP, VP, I64, VP, P(ctypes.c_uint64)], INT),
         "rs_server_poll": ([VP, ctypes.c_uint64, P(INT)], INT),
@@ -168,6 +175,6 @@ def exported_symbols():
     return ["rs_version", "rs_last_error", "rs_workspace_bytes", "rs_make_map", "rs_ray_pixels",
             "rs_read_stats", "rs_make_map_noalloc", "rs_profile_enable", "rs_profile_read", "rs_tune", "rs_set_shape",
             "rs_tune_save", "rs_tune_load", "rs_batch_workspace_bytes", "rs_make_maps",
-            "rs_batch_read_stats", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
+            "rs_batch_read_stats", "rs_tune_batch", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
             "rs_server_cancel", "rs_server_get_stats", "rs_server_destroy", "rs_rays_per_pixel", "rs_map_max",
             "rs_map_histogram", "rs_delta_m", "rs_compare_workspace_bytes", "rs_compare_maps"]

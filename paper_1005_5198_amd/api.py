@@ -15,6 +15,7 @@ import torch
 from . import _lib as L
 
 MODES = {"fp32": L.RS_FP32, "mixed": L.RS_MIXED, "farfield": L.RS_FARFIELD}
+SHAPES = {0: (4, 2), 1: (4, 4), 2: (8, 2), 3: (8, 4)}   # rays per lane (x, y) of each thread shape
 
 
 def to_params(p: dict, mode: str = "mixed", accumulate: bool = False, exact_recheck: bool = False) -> L.MapParams:
@@ -272,6 +273,16 @@ class Batch:
                                      self.workspace.numel(), _stream_handle(stream)))
         _hold(stream, self.workspace, *self.outs, *(t for pair in self.lenses for t in pair))
         return self.outs
+
+    def tune(self, sample_rays: int = 1 << 20, stream=None) -> dict:
+        """Time every thread shape and persistent grid on a band of every map (the maps are
+        overwritten) and cache the fastest for batches like this one."""
+        r = L.TuneBatchResult()
+        L.check(L.lib().rs_tune_batch(self.reqs, len(self.params), self.workspace.data_ptr(), self.workspace.numel(),
+                                      int(sample_rays), _stream_handle(stream), ctypes.byref(r)))
+        cands = [dict(shape=r.shape[k], rays_per_lane=SHAPES[r.shape[k]], blocks_per_cu=r.blocks_per_cu[k],
+                      ms=r.ms[k]) for k in range(r.n)]
+        return dict(best=cands[r.best], candidates=cands, sample_interactions=r.sample_interactions)
 
     def stats(self, stream=None):
         n = len(self.params)

@@ -16,11 +16,16 @@ import torch
 from . import workloads as w
 
 
-def batched(rs, n_maps: int = 64, mode: str = "mixed", repeats: int = 1, check: bool = True) -> dict:
+def batched(rs, n_maps: int = 64, mode: str = "mixed", repeats: int = 1, check: bool = True,
+            tune: bool = True) -> dict:
+    """The config-3 batch in one persistent launch (tuned first: thread shape and persistent
+    grid timed on a band of every map) against the same maps one at a time (the single-map
+    tuner's choice per map signature)."""
     specs = w.config3(n_maps)
     items = [(s.params, s.lens_xy, s.lens_m) for s in specs]
     b = rs.Batch(items, mode=mode)
     inter = b.interactions
+    tuned = b.tune() if tune else None
     b.run()
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -52,7 +57,11 @@ def batched(rs, n_maps: int = 64, mode: str = "mixed", repeats: int = 1, check: 
             "batched_maps_per_s": n_maps / dt_batch, "batched_value": inter / dt_batch,
             "plain_maps_per_s": n_maps / dt_plain, "plain_value": inter / dt_plain,
             "speedup": dt_plain / dt_batch, "batched_s": dt_batch, "plain_s": dt_plain,
-            "identical_to_plain": identical}
+            "identical_to_plain": identical,
+            "tuned": None if tuned is None else {
+                "rays_per_lane": tuned["best"]["rays_per_lane"], "blocks_per_cu": tuned["best"]["blocks_per_cu"],
+                "sample_ms": tuned["best"]["ms"], "candidates": len(tuned["candidates"]),
+                "sample_interactions": tuned["sample_interactions"]}}
 
 
 def _percentiles(lat):

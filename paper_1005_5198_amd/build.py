@@ -29,7 +29,7 @@ COMPILE_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
                  "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                  "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable", "-Wno-pass-failed",
                  f"-I{INCLUDE}", f"-I{CSRC}"]
-LINK_FLAGS = [f"--offload-arch={ARCH}", "-fPIC", "-shared", "-lpthread"]
+LINK_FLAGS = [f"--offload-arch={ARCH}", "-fPIC", "-shared", "-lpthread", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 FLAGS = COMPILE_FLAGS + ["-shared", "-lpthread"]
 NOISE = "is not a recognized feature for this target"
 

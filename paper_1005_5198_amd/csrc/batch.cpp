@@ -4,6 +4,7 @@
 // fill -> persistent deflection -> batched FP64 re-check.
 #include "rs_internal.h"
 #include "rayshoot.h"
+#include "rs_debug.h"
 
 #include <algorithm>
 #include <numeric>
@@ -14,7 +15,8 @@ namespace rs {
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int validate(const rs_map_params *p, int64_t n_lens);
-int choose_shape(int mode, bool unit, int64_t n_lens);
+int choose_batch(int mode, bool unit, int64_t n_lens, int64_t tiles);
+void remember_batch(int mode, bool unit, int64_t n_lens, int64_t tiles, int choice);
 void profile_begin(hipStream_t stream, void **token);
 int profile_end(hipStream_t stream, void *token, double interactions);
 
@@ -49,7 +51,12 @@ size_t rs_batch_workspace_bytes(const rs_map_request *reqs, int32_t n) {
     return batch_bytes(reqs, n);
 }
 
-int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t workspace_bytes, void *stream) {
+// The batch's launches. choice < 0: the tuned (or default) kernel configuration;
+// otherwise shape = choice % 16, blocks per CU = choice / 16 (0 = as many as fit).
+// deflection_only: no re-check (the tuner's timing runs); kernel_ms: time the
+// persistent deflection launch with events and synchronise.
+static int enqueue_batch(const rs_map_request *reqs, int32_t n, void *workspace, size_t workspace_bytes,
+                         hipStream_t s, int choice, bool deflection_only, float *kernel_ms) {
     if (!reqs || n < 1 || n > 65536) return fail(RS_EINVAL, "need 1..65536 requests");
     if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
     const int mode = reqs[0].params.mode;
@@ -124,7 +131,7 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
         words += m.n_words;
         interactions += (double)W * (double)H * (double)r.n_lens;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    Range range("rs_make_maps");
     hipError_t e = hipMemcpyAsync(ws + batch_maps_offset(), maps.data(), sizeof(BatchMap) * (size_t)n,
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "uploading batch descriptors");
@@ -143,20 +150,97 @@ int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t 
     e = launch_batch_fill(b, workspace, n, s);
     if (e != hipSuccess) return hip_fail(e, "batch fill kernel");
     const rs_map_request &heavy = reqs[order[0]];
-    const int shape = choose_shape(mode, heavy.lens_m == nullptr, heavy.n_lens);
+    if (choice < 0) choice = choose_batch(mode, heavy.lens_m == nullptr, heavy.n_lens, tiles);
+    const int shape = choice % 16, blocks_per_cu = choice / 16;
+    debug_print(1, "batch of %d maps, %lld tiles, %.3e interactions, mode %d: shape %d, %d blocks per CU%s", n,
+                (long long)tiles, interactions, mode, shape, blocks_per_cu, blocks_per_cu ? "" : " (as many as fit)");
     void *tok = nullptr;
-    profile_begin(s, &tok);
-    e = launch_shoot_batch(b, shape, 0, s);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (kernel_ms) {
+        if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
+            hipEventRecord(ev[0], s) != hipSuccess) {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return fail(RS_EHIP, "timing events");
+        }
+    } else {
+        profile_begin(s, &tok);
+    }
+    e = launch_shoot_batch(b, shape, blocks_per_cu, s);
     // profile_end takes the event in every case, also after a failed launch
-    int rc = profile_end(s, tok, interactions);
+    int rc = kernel_ms ? RS_OK : profile_end(s, tok, interactions);
+    if (kernel_ms) {
+        *kernel_ms = 0.0f;
+        hipError_t t = hipEventRecord(ev[1], s);
+        if (t == hipSuccess) t = hipEventSynchronize(ev[1]);
+        if (t == hipSuccess) t = hipEventElapsedTime(kernel_ms, ev[0], ev[1]);
+        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+        if (e == hipSuccess && t != hipSuccess) return hip_fail(t, "timing the batched kernel");
+    }
     if (e != hipSuccess) return hip_fail(e, "batched deflection kernel");
     if (rc) return rc;
-    if (mode == RS_MIXED) {
+    if (mode == RS_MIXED && !deflection_only) {
         e = launch_batch_super(b, s);
         if (e != hipSuccess) return hip_fail(e, "batched super-patch kernel");
         e = launch_recheck_batch(b, s);
         if (e != hipSuccess) return hip_fail(e, "batched re-check kernels");
     }
+    return RS_OK;
+}
+
+int rs_make_maps(const rs_map_request *reqs, int32_t n, void *workspace, size_t workspace_bytes, void *stream) {
+    return enqueue_batch(reqs, n, workspace, workspace_bytes, static_cast<hipStream_t>(stream), -1, false, nullptr);
+}
+
+int rs_tune_batch(const rs_map_request *requests, int32_t n, void *workspace, size_t workspace_bytes,
+                  int64_t sample_rays, void *stream, rs_tune_batch_result *result_host) {
+    if (!requests || !result_host || n < 1 || n > 65536) return fail(RS_EINVAL, "bad arguments");
+    if (sample_rays <= 0) sample_rays = int64_t(1) << 20;
+    // The sample: a band of whole 32-row patch rows from the middle of each window.
+    std::vector<rs_map_request> sample(requests, requests + n);
+    double inter = 0.0;
+    int64_t full_tiles = 0;
+    for (rs_map_request &r : sample) {
+        rs_map_params &p = r.params;
+        const int64_t W = p.i1 - p.i0, H = p.j1 - p.j0;
+        if (W > 0 && H > 0) full_tiles += ((W + PATCH_X - 1) / PATCH_X) * ((H + PATCH_Y - 1) / PATCH_Y);
+        if (W <= 0 || H <= 0) continue;
+        int64_t rows = std::max<int64_t>(PATCH_Y, sample_rays / W / PATCH_Y * PATCH_Y);
+        rows = std::min(rows, H);
+        p.j0 += (H - rows) / 2 / PATCH_Y * PATCH_Y;
+        p.j1 = p.j0 + rows;
+        p.flags &= ~RS_ACCUMULATE;
+        inter += (double)W * (double)rows * (double)r.n_lens;
+    }
+    if (batch_bytes(sample.data(), n) > workspace_bytes) return fail(RS_ENOMEM, "workspace too small for the sample");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rs_tune_batch_result res{};
+    res.sample_interactions = inter;
+    const int bpcs[3] = {0, 3, 2};   // as many blocks per CU as fit, then fewer
+    int best = -1;
+    for (int shape = 0; shape < N_SHAPES; ++shape)
+        for (int bpc : bpcs) {
+            if (res.n >= RS_MAX_BATCH_CHOICES) break;
+            const int choice = shape + 16 * bpc;
+            float ms = 0.0f, best_ms = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {   // first run warms up; keep the fastest of the rest
+                const int rc = enqueue_batch(sample.data(), n, workspace, workspace_bytes, s, choice, true, &ms);
+                if (rc) return rc;
+                if (rep > 0 && ms < best_ms) best_ms = ms;
+            }
+            const int k = res.n++;
+            res.shape[k] = shape;
+            res.blocks_per_cu[k] = bpc;
+            res.ms[k] = best_ms;
+            if (best < 0 || best_ms < res.ms[best]) best = k;
+        }
+    res.best = best;
+    const rs_map_request *heavy = &requests[0];
+    for (int32_t k = 1; k < n; ++k)
+        if (requests[k].n_lens > heavy->n_lens) heavy = &requests[k];
+    remember_batch(requests[0].params.mode, heavy->lens_m == nullptr, heavy->n_lens, full_tiles,
+                   res.shape[best] + 16 * res.blocks_per_cu[best]);
+    *result_host = res;
     return RS_OK;
 }
 

@@ -245,7 +245,8 @@ hipError_t launch_recheck_far(const ShootArgs &a, uint32_t *qlive, int64_t max_r
 hipError_t launch_super_records(const ShootArgs &a, int64_t n_super, hipStream_t stream);
 
 hipError_t launch_batch_fill(const BatchArgs &b, void *workspace, int32_t n_maps, hipStream_t stream);
-hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream);
+// Persistent launch: blocks_per_cu <= 0 fills every CU with as many blocks as fit.
+hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int blocks_per_cu, hipStream_t stream);
 hipError_t launch_recheck_batch(const BatchArgs &b, hipStream_t stream);
 // Mixed batches: super-patch records of every map that flagged rays.
 hipError_t launch_batch_super(const BatchArgs &b, hipStream_t stream);

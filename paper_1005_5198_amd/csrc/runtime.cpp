@@ -3,6 +3,7 @@
 // (zero map and counters -> per chunk: deflection kernel, FP64 re-check).
 #include "rs_internal.h"
 #include "rayshoot.h"
+#include "rs_debug.h"
 #include "rs_plan.h"
 
 #include <cmath>
@@ -103,7 +104,7 @@ struct EventPair {
     }
 };
 
-int choose_shape(int mode, bool unit, int64_t n_lens);
+int choose_shape(int mode, bool unit, int64_t n_lens, int64_t patches);
 
 // Enqueue the whole map (or pixel) computation. map may be null when pix is set.
 // shape < 0 picks the tuned or default thread shape. When kernel_ms is given,
@@ -160,6 +161,7 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
                            uint32_t *map, int32_t *pix, void *workspace, hipStream_t stream, int shape,
                            float *kernel_ms, const Plan &pl, bool profile) {
     int rc = RS_OK;
+    Range range(pix ? "rs_ray_pixels" : "rs_make_map");
 
     const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
     hipError_t e =
@@ -247,7 +249,12 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
             if (e != hipSuccess) return hip_fail(e, "super-patch records");
         }
     }
-    if (shape < 0 && !pl.random && p->mode != RS_FARFIELD) shape = choose_shape(p->mode, lens_m == nullptr, n_lens);
+    if (shape < 0 && !pl.random && p->mode != RS_FARFIELD)
+        shape = choose_shape(p->mode, lens_m == nullptr, n_lens, (pl.W + PATCH_X - 1) / PATCH_X * ((pl.H + PATCH_Y - 1) / PATCH_Y));
+    debug_print(1, "map %lldx%lld rays, %lld lenses%s, mode %d%s: %lld launch(es) of %lld rows, workspace %zu B, shape %d",
+                (long long)pl.W, (long long)pl.H, (long long)n_lens, lens_m ? " with masses" : "", p->mode,
+                pl.random ? ", random rays" : "", (long long)pl.n_chunks, (long long)pl.rows_per_chunk, pl.bytes,
+                shape);
     EventPair ev;
     if (kernel_ms) {
         *kernel_ms = 0.0f;

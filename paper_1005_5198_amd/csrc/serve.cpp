@@ -17,6 +17,7 @@
 // same map made alone.
 #include "rs_internal.h"
 #include "rayshoot.h"
+#include "rs_debug.h"
 #include "rs_server_core.h"
 
 #include <cstring>
@@ -78,6 +79,9 @@ class HipExecutor final : public serve::Executor {
     int bind_thread() override { return hipSetDevice(device_) == hipSuccess ? RS_OK : RS_EHIP; }
 
     int admit(const Request &r) override {
+        Range range("serve:admit");
+        debug_print(2, "server: admit request %llu (%lld lenses, %lldx%lld px)", (unsigned long long)r.ticket,
+                    (long long)r.n_lens, (long long)r.p.npx, (long long)r.p.npy);
         hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(pool_ + r.off_map), r.p.npx * r.p.npy, admit_);
         if (e == hipSuccess && r.has_lens)
             e = hipMemcpyAsync(pool_ + r.off_lens, r.lens_xy.data(), 16 * (size_t)r.n_lens, hipMemcpyHostToDevice,
@@ -90,6 +94,7 @@ class HipExecutor final : public serve::Executor {
     }
 
     int launch(const std::vector<StepItem> &items, int slot, void **out) override {
+        Range range("serve:launch_step");
         std::vector<rs_map_request> batch;
         batch.reserve(items.size());
         for (const StepItem &it : items) {
@@ -106,6 +111,12 @@ class HipExecutor final : public serve::Executor {
             batch.push_back(q);
         }
         const int32_t n = (int32_t)batch.size();
+        if (debug_level() >= 2) {
+            double inter = 0.0;
+            for (const rs_map_request &q : batch)
+                inter += (double)(q.params.i1 - q.params.i0) * (double)(q.params.j1 - q.params.j0) * (double)q.n_lens;
+            debug_print(2, "server: step on slot %d, %d slices, %.3e interactions", slot, n, inter);
+        }
         const size_t need = rs_batch_workspace_bytes(batch.data(), n);
         if (!need) return fail(RS_EINVAL, "invalid step");
         if (need > ws_bytes_[slot]) {
@@ -169,6 +180,7 @@ class HipExecutor final : public serve::Executor {
     }
 
     void retire(void *h, double *own_ms, double *end_ms, std::vector<rs_map_stats> *stats) override {
+        Range range("serve:retire");
         Step *st = static_cast<Step *>(h);
         float own = 0.0f, end = 0.0f;
         *own_ms = hipEventElapsedTime(&own, st->ev_start, st->ev_end) == hipSuccess ? own : 0.0;
@@ -198,6 +210,7 @@ class HipExecutor final : public serve::Executor {
     }
 
     int copy_map(const Request &r, uint32_t *host) override {
+        Range range("serve:copy_map");
         const size_t bytes = 4 * (size_t)(r.p.npx * r.p.npy);
         // every step that touched the map has retired (its end event completed)
         if (hipMemcpyAsync(host, pool_ + r.off_map, bytes, hipMemcpyDeviceToHost, copy_) != hipSuccess ||

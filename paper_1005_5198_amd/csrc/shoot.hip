@@ -426,9 +426,10 @@ const ShapeInfo &shape_info(int shape) {
     return table[(shape >= 0 && shape < N_SHAPES) ? shape : 0];
 }
 
-// Resident blocks of a persistent kernel: every CU times the blocks that fit on it.
+// Blocks of a persistent kernel: every CU times min(blocks_per_cu, the blocks that
+// fit on it); blocks_per_cu <= 0 takes all that fit.
 template <class K>
-static int resident_blocks(K kernel, int threads) {
+static int persistent_blocks(K kernel, int threads, int blocks_per_cu) {
     static int n_cu = 0;
     if (n_cu == 0) {
         int dev = 0;
@@ -439,36 +440,37 @@ static int resident_blocks(K kernel, int threads) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
         per_cu = 2;
+    if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
     return n_cu * per_cu;
 }
 
 template <int RX, int RY, int WX, int WY, bool UNIT, int MODE>
-static void launch_batch_variant(const BatchArgs &b, int grid_blocks, hipStream_t stream) {
+static void launch_batch_variant(const BatchArgs &b, int blocks_per_cu, hipStream_t stream) {
     const int threads = 64 * WX * WY;
     auto k = shoot_batch_kernel<RX, RY, WX, WY, UNIT, MODE>;
-    if (grid_blocks <= 0) grid_blocks = resident_blocks(k, threads);
+    int grid_blocks = persistent_blocks(k, threads, blocks_per_cu);
     if ((int64_t)grid_blocks > b.total_tiles) grid_blocks = (int)b.total_tiles;
     hipLaunchKernelGGL(k, dim3((unsigned)grid_blocks), dim3(threads), 0, stream, b);
 }
 
 template <int RX, int RY, int WX, int WY>
-static void launch_batch_shape(const BatchArgs &b, int grid_blocks, hipStream_t stream) {
+static void launch_batch_shape(const BatchArgs &b, int blocks_per_cu, hipStream_t stream) {
     if (b.unit_masses) {
-        if (b.mode == 0) launch_batch_variant<RX, RY, WX, WY, true, 0>(b, grid_blocks, stream);
-        else launch_batch_variant<RX, RY, WX, WY, true, 1>(b, grid_blocks, stream);
+        if (b.mode == 0) launch_batch_variant<RX, RY, WX, WY, true, 0>(b, blocks_per_cu, stream);
+        else launch_batch_variant<RX, RY, WX, WY, true, 1>(b, blocks_per_cu, stream);
     } else {
-        if (b.mode == 0) launch_batch_variant<RX, RY, WX, WY, false, 0>(b, grid_blocks, stream);
-        else launch_batch_variant<RX, RY, WX, WY, false, 1>(b, grid_blocks, stream);
+        if (b.mode == 0) launch_batch_variant<RX, RY, WX, WY, false, 0>(b, blocks_per_cu, stream);
+        else launch_batch_variant<RX, RY, WX, WY, false, 1>(b, blocks_per_cu, stream);
     }
 }
 
-hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int grid_blocks, hipStream_t stream) {
+hipError_t launch_shoot_batch(const BatchArgs &b, int shape, int blocks_per_cu, hipStream_t stream) {
     if (b.total_tiles <= 0) return hipSuccess;
     switch (shape) {
-        case 1: launch_batch_shape<4, 4, 2, 1>(b, grid_blocks, stream); break;
-        case 2: launch_batch_shape<8, 2, 1, 2>(b, grid_blocks, stream); break;
-        case 3: launch_batch_shape<8, 4, 1, 1>(b, grid_blocks, stream); break;
-        default: launch_batch_shape<4, 2, 2, 2>(b, grid_blocks, stream); break;
+        case 1: launch_batch_shape<4, 4, 2, 1>(b, blocks_per_cu, stream); break;
+        case 2: launch_batch_shape<8, 2, 1, 2>(b, blocks_per_cu, stream); break;
+        case 3: launch_batch_shape<8, 4, 1, 1>(b, blocks_per_cu, stream); break;
+        default: launch_batch_shape<4, 2, 2, 2>(b, blocks_per_cu, stream); break;
     }
     return hipGetLastError();
 }

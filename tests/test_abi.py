@@ -96,16 +96,23 @@ def test_make_map_rejects_null_outputs(lib):
 
 def test_tune_cache_file_validation(lib, tmp_path):
     from paper_1005_5198_amd import api, _lib
-    bad = tmp_path / "bad.txt"
-    bad.write_text("1 1 9 77\n")
-    with pytest.raises(_lib.RayshootError):
-        api.tune_load(str(bad))
+    # lines: kind mode unit n_bucket patch_bucket choice
+    for text in ("0 1 1 9 15 77\n",      # shape 13 does not exist
+                 "0 1 1 9 15 34\n",      # single maps take no blocks-per-CU part
+                 "2 1 1 9 15 1\n",       # kind 2
+                 "0 1 1 9 15\n",         # five fields
+                 "0 1 1 9 15 1\n1 1 1\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        with pytest.raises(_lib.RayshootError):
+            api.tune_load(str(bad))
     good = tmp_path / "good.txt"
-    good.write_text("1 1 9 2\n0 1 14 1\n")
+    good.write_text("0 1 1 9 15 2\n1 1 0 14 11 49\n")
     api.tune_load(str(good))
     out = tmp_path / "out.txt"
     api.tune_save(str(out))
-    assert "1 1 9 2" in out.read_text()
+    text = out.read_text()
+    assert "0 1 1 9 15 2" in text and "1 1 0 14 11 49" in text
 
 
 def test_set_shape_range(lib):
@@ -231,3 +238,20 @@ def test_noalloc_entry_point_rejects_before_device_work(lib):
     c = api.to_params(wide, "fp32")
     n = lib.rs_workspace_bytes(ctypes.byref(c), 462)
     assert 0 < n <= _lib.RS_NOALLOC_SCRATCH_BYTES
+
+
+def test_tune_cache_from_environment(tmp_path):
+    """RAYSHOOT_TUNE_CACHE is loaded on first use (here: the first save) in a fresh process."""
+    import subprocess
+    import sys
+    cache = tmp_path / "cache.txt"
+    cache.write_text("0 1 1 14 15 2\n1 1 1 14 16 35\n")
+    out = tmp_path / "out.txt"
+    code = ("import sys; sys.path.insert(0, %r); from paper_1005_5198_amd import api; api.tune_save(%r)"
+            % (ROOT, str(out)))
+    env = dict(os.environ, RAYSHOOT_TUNE_CACHE=str(cache), RAYSHOOT_DEBUG="1")
+    p = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, p.stderr[-2000:]
+    text = out.read_text()
+    assert "0 1 1 14 15 2" in text and "1 1 1 14 16 35" in text
+    assert "[rayshoot] tune cache" in p.stderr

@@ -381,8 +381,31 @@ def test_tuner_picks_and_persists(rs, tmp_path):
     path = str(tmp_path / "tune.txt")
     rs.tune_save(path)
     rs.tune_load(path)
-    text = open(path).read().split()
-    assert len(text) % 4 == 0 and len(text) >= 4
+    lines = [l.split() for l in open(path).read().splitlines() if l.strip()]
+    assert lines and all(len(l) == 6 for l in lines)
+    assert any(l[0] == "0" and int(l[5]) == res["best"] for l in lines)
+
+
+def test_batch_tuner_picks_and_maps_stay_exact(rs, tmp_path):
+    """The batch tuner times every thread shape and persistent grid on a band of every map;
+    the batch then runs with its choice, and the maps still equal the single maps (mixed:
+    the oracle's too)."""
+    specs = _batch_specs()
+    items = [(x.params, x.lens_xy, x.lens_m) for x in specs]
+    b = rs.Batch(items, mode="mixed")
+    res = b.tune(sample_rays=1 << 16)
+    say("batch tune:", res["best"], len(res["candidates"]), "candidates")
+    assert len(res["candidates"]) == 12 and res["sample_interactions"] > 0
+    assert all(c["ms"] > 0 for c in res["candidates"])
+    assert res["best"]["ms"] == min(c["ms"] for c in res["candidates"])
+    outs = b.run()
+    for x, o in zip(specs, outs):
+        single = rs.make_map(x.params, x.lens_xy, x.lens_m, mode="mixed").cpu().numpy()
+        assert np.array_equal(o.cpu().numpy(), single), x.name
+    path = str(tmp_path / "tune.txt")
+    rs.tune_save(path)
+    lines = [l.split() for l in open(path).read().splitlines() if l.strip()]
+    assert any(l[0] == "1" for l in lines)
 
 
 def _batch_specs():
