@@ -79,8 +79,8 @@ struct FarAcc {
         sdef += am * 1.4142135623730951 / (ad - h);
         nfar += 1.0;
     }
-    // Sum of one wave's lanes (butterfly) into out[FAR_REC] (shared), written by lane 0.
-    __device__ void reduce_wave(double *out) {
+    // Sum over the wave's lanes (butterfly): every lane ends with the totals.
+    __device__ void butterfly() {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
@@ -92,34 +92,12 @@ struct FarAcc {
             trunc += __shfl_xor(trunc, off);
             sdef += __shfl_xor(sdef, off);
             nfar += __shfl_xor(nfar, off);
-        }
-        if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-            for (int n = 0; n < FAR_P; ++n) {
-                out[n] = c1[n];
-                out[FAR_P + n] = c2[n];
-            }
-            out[2 * FAR_P] = sfar;
-            out[2 * FAR_P + 1] = trunc;
-            out[2 * FAR_P + 2] = sdef;
-            out[2 * FAR_P + 3] = nfar;
         }
     }
     // Block sum into out[FAR_REC] (shared); lanes by butterfly, then waves in index order.
     __device__ void reduce(double (*part)[FAR_REC], double *out) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-            for (int n = 0; n < FAR_P; ++n) {
-                c1[n] += __shfl_xor(c1[n], off);
-                c2[n] += __shfl_xor(c2[n], off);
-            }
-            sfar += __shfl_xor(sfar, off);
-            trunc += __shfl_xor(trunc, off);
-            sdef += __shfl_xor(sdef, off);
-            nfar += __shfl_xor(nfar, off);
-        }
+        butterfly();
         if (lane == 0) {
 #pragma unroll
             for (int n = 0; n < FAR_P; ++n) {
@@ -206,120 +184,185 @@ __global__ __launch_bounds__(FAR_THREADS) void batch_super_kernel(const BatchArg
     build_super<UNIT>(a, t - m.super_begin, sm);
 }
 
+// One patch of a far-field launch: first ray (ib, jb), centre (ox, oy), half-
+// diagonal h (one ray spacing of slack on each side), the radius inside which
+// lenses are summed directly, and the super-patch that holds it. Window widths
+// stay below 2^22 rays and launches below 2^31 patches, so 32-bit indices hold.
+struct PatchFrame {
+    int64_t ib, jb, sp;
+    double ox, oy, h, near_r2;
+};
+
+__device__ __forceinline__ PatchFrame patch_frame(const ShootArgs &a, int64_t patch) {
+    PatchFrame f;
+    const int32_t nbx = (int32_t)a.nbx, p = (int32_t)patch;
+    const int32_t pbx = p % nbx, pby = p / nbx;
+    f.ib = a.i0 + (int64_t)pbx * PATCH_X;
+    f.jb = a.jc0 + (int64_t)pby * PATCH_Y;
+    f.sp = (int64_t)(pby / FF_SP_Y) * a.ff_sbx + pbx / FF_SP_X;
+    f.ox = a.sx0 + ((double)f.ib + 0.5 * PATCH_X) * a.spx;
+    f.oy = a.sy0 + ((double)f.jb + 0.5 * PATCH_Y) * a.spy;
+    const double hx = (0.5 * PATCH_X + 1.0) * a.spx;
+    const double hy = (0.5 * PATCH_Y + 1.0) * a.spy;
+    f.h = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
+    f.near_r2 = (FAR_RATIO * f.h) * (FAR_RATIO * f.h);
+    return f;
+}
+
+// The candidates of a patch: the super-patch's list, or, when that list
+// overflowed, every lens the super-patch did not expand (the same test the
+// super kernel made). Calls visit(k, X, Y) for candidate q of n.
+struct Candidates {
+    const global_i32 *list;
+    int64_t n;
+    bool scan_all;
+    double cx, cy, super_r2;
+};
+
+__device__ __forceinline__ Candidates candidates(const ShootArgs &a, int64_t sp) {
+    Candidates c;
+    double H;
+    super_geometry(a, sp, c.cx, c.cy, H);
+    c.super_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
+    c.list = (const global_i32 *)(a.ff_near + sp * (int64_t)(1 + a.ff_cap));
+    const int32_t listed = c.list[0];
+    c.scan_all = listed > a.ff_cap;
+    c.n = c.scan_all ? a.n_lens : listed;
+    return c;
+}
+
+// Candidate q: its lens index and position; false when an overflowed list's
+// scan meets a lens the super-patch expanded.
+__device__ __forceinline__ bool candidate(const ShootArgs &a, const Candidates &c, int64_t q, int64_t &k, double &X,
+                                          double &Y) {
+    k = c.scan_all ? q : (int64_t)c.list[1 + q];
+    X = ((global_double *)a.lens_xy)[2 * k];
+    Y = ((global_double *)a.lens_xy)[2 * k + 1];
+    if (c.scan_all) {
+        const double e1 = c.cx - X, e2 = c.cy - Y;
+        if (e1 * e1 + e2 * e2 >= c.super_r2) return false;
+    }
+    return true;
+}
+
+// Level 2, part 1: the record of each patch, one wave per patch. The candidates
+// farther than FAR_RATIO h from the patch centre add their own expansion about
+// it; the super-patch expansion is re-centred exactly on it,
+//   sum_n C_n (e + v)^n = sum_m v^m sum_{n>=m} binom(n, m) e^(n-m) C_n,
+// v = -w = z0 - z, e = zS - z0; the record holds the sum of both and the bound
+// terms of both levels (truncation, and rounding of the coefficients, the
+// translation and the evaluation, with per-level factors and generous constants).
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_patch_kernel(const ShootArgs a, int64_t patches) {
+    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+    const int lane = threadIdx.x & 63;
+    const int64_t patch = (int64_t)blockIdx.x * (FAR_THREADS / 64) + (threadIdx.x >> 6);
+    if (patch >= patches) return;   // the whole wave
+    const PatchFrame f = patch_frame(a, patch);
+    const Candidates c = candidates(a, f.sp);
+    FarAcc acc;
+    acc.zero();
+    for (int64_t q = lane; q < c.n; q += 64) {
+        int64_t k;
+        double X, Y;
+        if (!candidate(a, c, q, k, X, Y)) continue;
+        const double d1 = f.ox - X, d2 = f.oy - Y;
+        const double r2 = d1 * d1 + d2 * d2;
+        if (!(r2 >= f.near_r2)) continue;   // summed directly by the ray kernel
+        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
+        acc.add(d1, d2, r2, m, f.h);
+    }
+    acc.butterfly();   // every lane now holds the wave's sums
+    const global_double *sc = (const global_double *)(a.ff_super + f.sp * (int64_t)FAR_REC);
+    double *rec = a.ff_patch + patch * (int64_t)FF_PATCH_DOUBLES;
+    if (lane < FAR_P) {
+        const int mm = lane;
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int n = 0; n < FAR_P; ++n) {
+            if (n == mm) {
+                p1 = acc.c1[n];
+                p2 = acc.c2[n];
+            }
+        }
+        double cx, cy, H;
+        super_geometry(a, f.sp, cx, cy, H);
+        const double e1 = cx - f.ox, e2 = cy - f.oy;
+        double s1 = 0.0, s2 = 0.0;
+        double g1 = 1.0, g2 = 0.0;   // e^(n-m)
+        for (int n = mm; n < FAR_P; ++n) {
+            const double binom = BINOM[n][mm];   // exact in FP64 for n < 16
+            const double C1 = sc[n], C2 = sc[FAR_P + n];
+            s1 = __builtin_fma(binom, g1 * C1 - g2 * C2, s1);
+            s2 = __builtin_fma(binom, g1 * C2 + g2 * C1, s2);
+            const double q1 = g1 * e1 - g2 * e2, q2 = g1 * e2 + g2 * e1;
+            g1 = q1;
+            g2 = q2;
+        }
+        rec[mm] = s1 + p1;
+        rec[FAR_P + mm] = s2 + p2;
+    } else if (lane == FAR_P) {
+        const double SFAR_S = sc[2 * FAR_P], TRUNC_S = sc[2 * FAR_P + 1], SDEF_S = sc[2 * FAR_P + 2];
+        const double NFAR_S = sc[2 * FAR_P + 3];
+        rec[2 * FAR_P] = SFAR_S + acc.sfar;
+        rec[2 * FAR_P + 1] = TRUNC_S + acc.trunc + (NFAR_S + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_S +
+                             (acc.nfar + 16.0 * FAR_P + 64.0) * U64 * 1.34 * acc.sfar;
+        rec[2 * FAR_P + 2] = SDEF_S + acc.sdef;
+        rec[2 * FAR_P + 3] = 0.0;
+    }
+}
+
 struct FarSmem {
     PixelTable table;            // the patch's counts per pixel (map mode)
     double near_x[NEAR_EXP], near_y[NEAR_EXP], near_m[NEAR_EXP];
+    double rec[FF_PATCH_DOUBLES];
+    unsigned long long n_in, n_out;
     int near_count;
-    double part[FAR_THREADS / 64][FAR_REC];
-    double pc[FAR_REC];          // this patch's own expansion (listed lenses)
-    double sc[FAR_REC];          // the super-patch's record
-    double tc[2 * FAR_P];        // total coefficients about z0
 };
 
-// One lens of the super-patch's list, seen from patch centre (ox, oy): far
-// from the patch -> its expansion (acc); else the LDS near list.
-template <bool UNIT>
-__device__ __forceinline__ void patch_candidate(const ShootArgs &a, int64_t k, double ox, double oy, double h,
-                                                double near_r2, FarAcc &acc, FarSmem &sm) {
-    const double X = a.lens_xy[2 * k], Y = a.lens_xy[2 * k + 1];
-    const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : a.lens_m[k];
-    const double d1 = ox - X, d2 = oy - Y;
-    const double r2 = d1 * d1 + d2 * d2;
-    if (!(r2 >= near_r2)) {
+// Level 2, part 2: the rays, one block per patch. The patch's near lenses go to
+// LDS (beyond NEAR_EXP of them the patch is re-checked whole); each thread then
+// takes 8 rays: the series (Horner in v), the near lenses directly, the pixel
+// decision against the bound, the count.
+template <bool UNIT, bool PIX>
+__global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArgs a) {
+    __shared__ FarSmem sm;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t patch = blockIdx.x;
+    const PatchFrame f = patch_frame(a, patch);
+    const int64_t ib = f.ib, jb = f.jb;
+    const double ox = f.ox, oy = f.oy;
+    const Candidates c = candidates(a, f.sp);
+    if (tid == 0) {
+        sm.near_count = 0;
+        sm.n_in = 0;
+        sm.n_out = 0;
+    }
+    if (tid < FF_PATCH_DOUBLES)
+        sm.rec[tid] = ((const global_double *)a.ff_patch)[patch * (int64_t)FF_PATCH_DOUBLES + tid];
+    if (!PIX) table_clear<FAR_THREADS>(sm.table, tid);
+    __syncthreads();
+    for (int64_t q = tid; q < c.n; q += FAR_THREADS) {
+        int64_t k;
+        double X, Y;
+        if (!candidate(a, c, q, k, X, Y)) continue;
+        const double d1 = ox - X, d2 = oy - Y;
+        const double r2 = d1 * d1 + d2 * d2;
+        if (r2 >= f.near_r2) continue;   // in the patch's expansion
+        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
         const int j = atomicAdd(&sm.near_count, 1);
         if (j < NEAR_EXP) {
             sm.near_x[j] = X;
             sm.near_y[j] = Y;
             sm.near_m[j] = m;
         }
-        return;
-    }
-    acc.add(d1, d2, r2, m, h);
-}
-
-// Level 2: one block per patch.
-template <bool UNIT, bool PIX>
-__global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArgs a) {
-    __shared__ FarSmem sm;
-    constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int64_t patch = blockIdx.x;
-    const int64_t pbx = patch % a.nbx, pby = patch / a.nbx;
-    const int64_t ib = a.i0 + pbx * PATCH_X;
-    const int64_t jb = a.jc0 + pby * PATCH_Y;
-    const double ox = a.sx0 + ((double)ib + 0.5 * PATCH_X) * a.spx;
-    const double oy = a.sy0 + ((double)jb + 0.5 * PATCH_Y) * a.spy;
-    const double hx = (0.5 * PATCH_X + 1.0) * a.spx;
-    const double hy = (0.5 * PATCH_Y + 1.0) * a.spy;
-    const double h = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
-    const double near_r2 = (FAR_RATIO * h) * (FAR_RATIO * h);
-    // This patch's super-patch.
-    const int64_t sp = (pby / FF_SP_Y) * a.ff_sbx + pbx / FF_SP_X;
-    double cx, cy, H;
-    super_geometry(a, sp, cx, cy, H);
-    const double super_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
-    const int32_t *list = a.ff_near + sp * (int64_t)(1 + a.ff_cap);
-    const int32_t listed = list[0];
-    const bool scan_all = listed > a.ff_cap;
-    if (tid == 0) sm.near_count = 0;
-    if (tid < FAR_REC) sm.sc[tid] = a.ff_super[sp * (int64_t)FAR_REC + tid];
-    if (!PIX) table_clear<FAR_THREADS>(sm.table, tid);
-    __syncthreads();
-
-    // The super-patch's nearer lenses: far from this patch -> its own expansion; else direct.
-    FarAcc acc;
-    acc.zero();
-    if (!scan_all) {
-        // The list (a few dozen lenses) by wave 0 alone, reduced over its 64 lanes:
-        // a block-wide reduction of the 36 sums costs more than the lenses.
-        if (tid < 64) {
-            for (int64_t q = lane; q < (int64_t)listed; q += 64)
-                patch_candidate<UNIT>(a, (int64_t)list[1 + q], ox, oy, h, near_r2, acc, sm);
-            acc.reduce_wave(sm.pc);
-        }
-        __syncthreads();
-    } else {
-        for (int64_t q = tid; q < a.n_lens; q += FAR_THREADS) {
-            const double e1 = cx - a.lens_xy[2 * q], e2 = cy - a.lens_xy[2 * q + 1];
-            if (e1 * e1 + e2 * e2 >= super_r2) continue;   // the same test the super kernel made
-            patch_candidate<UNIT>(a, q, ox, oy, h, near_r2, acc, sm);
-        }
-        acc.reduce(sm.part, sm.pc);
-    }
-
-    // Re-centre the super expansion: sum_n C_n (e + v)^n = sum_m v^m sum_{n>=m} binom(n,m) e^(n-m) C_n,
-    // v = -w = z0 - z, e = zS - z0; then add this patch's own coefficients.
-    if (tid < FAR_P) {
-        const int mm = tid;
-        const double e1 = cx - ox, e2 = cy - oy;
-        double s1 = 0.0, s2 = 0.0;
-        double g1 = 1.0, g2 = 0.0;   // e^(n-m)
-        for (int n = mm; n < FAR_P; ++n) {
-            const double binom = BINOM[n][mm];   // exact in FP64 for n < 16
-            s1 = __builtin_fma(binom, g1 * sm.sc[n] - g2 * sm.sc[FAR_P + n], s1);
-            s2 = __builtin_fma(binom, g1 * sm.sc[FAR_P + n] + g2 * sm.sc[n], s2);
-            const double q1 = g1 * e1 - g2 * e2, q2 = g1 * e2 + g2 * e1;
-            g1 = q1;
-            g2 = q2;
-        }
-        sm.tc[mm] = s1 + sm.pc[mm];
-        sm.tc[FAR_P + mm] = s2 + sm.pc[FAR_P + mm];
     }
     __syncthreads();
-    const double SFAR_S = sm.sc[2 * FAR_P], TRUNC_S = sm.sc[2 * FAR_P + 1], SDEF_S = sm.sc[2 * FAR_P + 2];
-    const double NFAR_S = sm.sc[2 * FAR_P + 3];
-    const double SFAR_P = sm.pc[2 * FAR_P], TRUNC_P = sm.pc[2 * FAR_P + 1], SDEF_P = sm.pc[2 * FAR_P + 2];
-    const double NFAR_P = sm.pc[2 * FAR_P + 3];
+    const double SFAR = sm.rec[2 * FAR_P], far_err = sm.rec[2 * FAR_P + 1], SDEF = sm.rec[2 * FAR_P + 2];
     const int n_near_all = sm.near_count;
     const bool all_flagged = n_near_all > NEAR_EXP;
     const int n_near = all_flagged ? 0 : n_near_all;
-    const double SFAR = SFAR_S + SFAR_P;
-    // Our own far-field error: truncation on both levels; rounding of the coefficients,
-    // the translation and the evaluation (per-level factors, generous constants).
-    const double far_err = TRUNC_S + TRUNC_P + (NFAR_S + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_S +
-                           (NFAR_P + 16.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_P;
-    const double SDEF = SDEF_S + SDEF_P;
 
     unsigned long long n_in = 0, n_out = 0;
     const int64_t W = a.i1 - a.i0;
@@ -347,8 +390,8 @@ __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArg
             double T1[FAR_P], T2[FAR_P];
 #pragma unroll
             for (int n = 0; n < FAR_P; ++n) {
-                T1[n] = sm.tc[n];
-                T2[n] = sm.tc[FAR_P + n];
+                T1[n] = sm.rec[n];
+                T2[n] = sm.rec[FAR_P + n];
             }
 #pragma unroll
             for (int k = 0; k < RPASS; ++k) {
@@ -404,15 +447,18 @@ __global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArg
             if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
         }
     }
-    if (!PIX) {
-        __syncthreads();   // every ray of the patch is in the table
-        table_flush<FAR_THREADS>(sm.table, a.map, tid);
-    }
     if (lane == 0) {
-        if (n_in) atomicAdd(a.counters + C_IN, n_in);
-        if (n_out) atomicAdd(a.counters + C_OUT, n_out);
+        if (n_in) atomicAdd(&sm.n_in, n_in);
+        if (n_out) atomicAdd(&sm.n_out, n_out);
+    }
+    __syncthreads();   // every ray of the patch is in the table and the block's counts
+    if (!PIX) table_flush<FAR_THREADS>(sm.table, a.map, tid);
+    if (tid == 0) {
+        if (sm.n_in) global_add(a.counters + C_IN, sm.n_in);
+        if (sm.n_out) global_add(a.counters + C_OUT, sm.n_out);
     }
 }
+
 
 // Re-check stage of the mixed mode on the regular grid, one thread per queued
 // ray (far_recheck_ray). A ray it places is binned and its entry marked
@@ -502,6 +548,11 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     if (unit) hipLaunchKernelGGL((farfield_super_kernel<true, false>), dim3((unsigned)n_super), block, 0, stream, a);
     else hipLaunchKernelGGL((farfield_super_kernel<false, false>), dim3((unsigned)n_super), block, 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 rec_grid((unsigned)((patches + FAR_THREADS / 64 - 1) / (FAR_THREADS / 64)));
+    if (unit) hipLaunchKernelGGL((farfield_patch_kernel<true>), rec_grid, block, 0, stream, a, patches);
+    else hipLaunchKernelGGL((farfield_patch_kernel<false>), rec_grid, block, 0, stream, a, patches);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)patches);
     if (unit) {

@@ -86,6 +86,11 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
         off += a256(sizeof(double) * FF_REC_DOUBLES * (size_t)pl.super_cap);
         pl.ff_near_off = off;
         off += a256(sizeof(int32_t) * (1 + (size_t)FF_NEAR_CAP) * (size_t)pl.super_cap);
+        if (p->mode == RS_FARFIELD) {
+            pl.patch_cap = nbx * nby;
+            pl.ff_patch_off = off;
+            off += a256(sizeof(double) * FF_PATCH_DOUBLES * (size_t)pl.patch_cap);
+        }
         pl.bytes = off;
     }
     if (pl.random && pl.n_chunks > 0) {

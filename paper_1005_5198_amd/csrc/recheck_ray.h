@@ -47,6 +47,18 @@ constexpr int CODE_SINGULAR = -2;
 // plain (generic) pointers; read through those, the lens loop compiles to flat
 // loads that wait on every memory counter each iteration.
 typedef __attribute__((address_space(1))) const double global_double;
+typedef __attribute__((address_space(1))) const int32_t global_i32;
+
+// Relaxed device-scope atomic adds through global (not flat) addressing, so a
+// later wait on LDS results does not also wait for these to complete.
+__device__ __forceinline__ void global_add(uint32_t *p, uint32_t v) {
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) uint32_t *)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void global_add(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long *)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ double lens_x(const RecheckArgs &a, int64_t k) {
     return ((global_double *)a.lens_xy)[2 * k];
 }

@@ -64,6 +64,7 @@ struct ShootArgs {
     double *ff_super;      // [n_super][2 * 16 + 4] coefficients and bound terms
     int32_t *ff_near;      // [n_super][1 + ff_cap] count, then indices of the nearer lenses
     int32_t ff_cap;        // list capacity per super-patch
+    double *ff_patch;      // far-field mode: [patches of the launch][FF_PATCH_DOUBLES] patch records
 };
 
 

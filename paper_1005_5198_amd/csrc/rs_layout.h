@@ -35,6 +35,10 @@ constexpr int FF_SP_Y = 4;
 constexpr int FF_NEAR_CAP = 4096;    // single maps (the far-field mode rescans all lenses beyond it)
 constexpr int FF_BATCH_CAP = 1024;   // batches (the re-check stage only; beyond it, the stage over every lens)
 constexpr int FF_REC_DOUBLES = 36;
+// Far-field mode, per 64 x 32-ray patch: the local expansion about the patch
+// centre (16 real, 16 imaginary coefficients), then the bound terms SFAR, far_err
+// and SDEF, and one spare double.
+constexpr int FF_PATCH_DOUBLES = 36;
 
 // Random rays: expected rays per bin (a block's capacity is 2048, so a bin
 // overflows it only beyond three standard deviations, about one bin in 3000,

@@ -29,6 +29,9 @@ struct Plan {
     // Far-field expansion: super-patch records and lens lists for the largest launch.
     int64_t super_cap = 0;
     size_t ff_super_off = 0, ff_near_off = 0;
+    // Far-field mode: the patch records of the largest launch.
+    int64_t patch_cap = 0;
+    size_t ff_patch_off = 0;
     size_t bytes = 0;
 };
 

@@ -242,6 +242,7 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
         a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
         a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
         a.ff_cap = FF_NEAR_CAP;
+        if (p->mode == RS_FARFIELD) a.ff_patch = reinterpret_cast<double *>(ws + pl.ff_patch_off);
         if (pl.random) {
             a.ff_i0 = 0;
             a.ff_j0 = 0;

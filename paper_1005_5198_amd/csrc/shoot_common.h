@@ -105,16 +105,24 @@ __device__ __forceinline__ void table_add(PixelTable &t, uint32_t *map, int p) {
         }
         s = (s + 1u) & (PT_SLOTS - 1);
     }
-    atomicAdd(map + p, 1u);
+    global_add(map + p, 1u);
 }
 static_assert(PT_SLOTS == 1 << 11, "the hash keeps 11 bits");
 
+// All slots' counts and keys are read before the first global atomic is issued.
 template <int THREADS>
 __device__ __forceinline__ void table_flush(const PixelTable &t, uint32_t *map, int tid) {
-    for (int s = tid; s < PT_SLOTS; s += THREADS) {
-        const uint32_t c = t.cnt[s];
-        if (c) atomicAdd(map + (t.key[s] - 1u), c);
+    static_assert(PT_SLOTS % THREADS == 0, "whole rounds of slots");
+    constexpr int R = PT_SLOTS / THREADS;
+    uint32_t c[R], k[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        c[r] = t.cnt[tid + r * THREADS];
+        k[r] = t.key[tid + r * THREADS];
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (c[r]) global_add(map + (k[r] - 1u), c[r]);
 }
 
 struct ShootSmem {

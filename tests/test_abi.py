@@ -172,14 +172,16 @@ def test_farfield_mode_validation(lib):
     s = w.config0()
     c = api.to_params(s.params, "farfield")
     assert c.mode == L.RS_FARFIELD
-    # it needs the re-check queue plus the super-patch records and lens lists; the mixed mode on
-    # the regular grid holds the same (its far-field re-check stage), its exact-only form does not
+    # it needs the re-check queue plus the super-patch records and lens lists, which the mixed
+    # mode on the regular grid holds too (its far-field re-check stage; its exact-only form does
+    # not), and a record of 36 doubles per 64 x 32-ray patch
     mixed = api.workspace_bytes(s.params, s.n_lens, "mixed")
     ff = lib.rs_workspace_bytes(ctypes.byref(c), s.n_lens)
     exact = lib.rs_workspace_bytes(ctypes.byref(api.to_params(s.params, "mixed", exact_recheck=True)), s.n_lens)
     n_super = -(-16 // 4) * -(-32 // 4)   # 1024^2 rays: 16 x 32 patches, 4 x 4 per super-patch
-    assert ff == mixed
-    assert ff >= exact + n_super * (36 * 8 + 4 * 4097)
+    n_patch = 16 * 32
+    assert ff == mixed + -(-n_patch * 36 * 8 // 256) * 256
+    assert ff >= exact + n_super * (36 * 8 + 4 * 4097) + n_patch * 36 * 8
     p = dict(s.params)
     p.update(random_rays=1)
     assert lib.rs_workspace_bytes(ctypes.byref(api.to_params(p, "farfield")), s.n_lens) == 0
