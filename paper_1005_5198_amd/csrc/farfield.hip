@@ -125,35 +125,88 @@ struct FarSuperSmem {
     int count;
 };
 
-// Records of super-patch sp: far lenses -> coefficients about zS; the others
-// -> the super-patch's lens list (a count above a.ff_cap means the list is
-// incomplete: the patches then scan every lens, the re-check stage passes).
-template <bool UNIT>
-__device__ inline void build_super(const ShootArgs &a, int64_t sp, FarSuperSmem &sm) {
-    double cx, cy, H;
-    super_geometry(a, sp, cx, cy, H);
+// Record of one level about (cx, cy) with half-diagonal H: of the candidates
+// (cand(q, k, X, Y) gives candidate q's lens, or false when q is none), those
+// farther than FAR_RATIO H add to the expansion C_n = sum m t^(n+1) and to the
+// bound sums; the others go to list (count in list[0]; a count above cap means
+// the list is incomplete and the level below scans every lens instead). With a
+// parent record about (pcx, pcy) (a level above, whose own candidates these
+// are), the parent's expansion is re-centred exactly on (cx, cy),
+//   E_m = sum_{n>=m} binom(n, m) e^(n-m) C_n, e = z_parent - z,
+// and added, and its bound sums are added to this level's. The sums stay valid
+// bounds below: their rounding constants allow for several translations.
+template <bool UNIT, class Cand>
+__device__ __forceinline__ void build_level(const ShootArgs &a, double cx, double cy, double H, int64_t n_cand, Cand cand,
+                                   int32_t *list, int cap, double *rec, const double *parent, double pcx, double pcy,
+                                   FarSuperSmem &sm) {
     const double near_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
-    int32_t *list = a.ff_near + sp * (int64_t)(1 + a.ff_cap);
     if (threadIdx.x == 0) sm.count = 0;
     __syncthreads();
     FarAcc acc;
     acc.zero();
-    for (int64_t k = threadIdx.x; k < a.n_lens; k += FAR_THREADS) {
-        const double X = ((global_double *)a.lens_xy)[2 * k], Y = ((global_double *)a.lens_xy)[2 * k + 1];
+#pragma unroll 1
+    for (int64_t q = threadIdx.x; q < n_cand; q += FAR_THREADS) {
+        int64_t k;
+        double X, Y;
+        if (!cand(q, k, X, Y)) continue;
         const double d1 = cx - X, d2 = cy - Y;
         const double r2 = d1 * d1 + d2 * d2;
         if (!(r2 >= near_r2)) {
-            const int q = atomicAdd(&sm.count, 1);
-            if (q < a.ff_cap) list[1 + q] = (int32_t)k;
+            const int j = atomicAdd(&sm.count, 1);
+            if (j < cap) list[1 + j] = (int32_t)k;
             continue;
         }
         const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
         acc.add(d1, d2, r2, m, H);
     }
     acc.reduce(sm.part, sm.out);
-    double *rec = a.ff_super + sp * (int64_t)FAR_REC;
-    if (threadIdx.x < FAR_REC) rec[threadIdx.x] = sm.out[threadIdx.x];
-    if (threadIdx.x == 0) list[0] = sm.count;
+    const int t = threadIdx.x;
+    if (parent == nullptr) {
+        if (t < FAR_REC) rec[t] = sm.out[t];
+    } else {
+        const global_double *P = (const global_double *)parent;
+        if (t < FAR_P) {
+            const double e1 = pcx - cx, e2 = pcy - cy;
+            double s1 = 0.0, s2 = 0.0;
+            double g1 = 1.0, g2 = 0.0;   // e^(n-m)
+            for (int n = t; n < FAR_P; ++n) {
+                const double binom = BINOM[n][t];   // exact in FP64 for n < 16
+                const double C1 = P[n], C2 = P[FAR_P + n];
+                s1 = __builtin_fma(binom, g1 * C1 - g2 * C2, s1);
+                s2 = __builtin_fma(binom, g1 * C2 + g2 * C1, s2);
+                const double q1 = g1 * e1 - g2 * e2, q2 = g1 * e2 + g2 * e1;
+                g1 = q1;
+                g2 = q2;
+            }
+            rec[t] = s1 + sm.out[t];
+            rec[FAR_P + t] = s2 + sm.out[FAR_P + t];
+        } else if (t < FAR_P + FAR_EXTRA) {
+            rec[2 * FAR_P + (t - FAR_P)] = P[2 * FAR_P + (t - FAR_P)] + sm.out[2 * FAR_P + (t - FAR_P)];
+        }
+    }
+    if (t == 0) list[0] = sm.count;
+}
+
+// Every lens is a candidate.
+struct AllLenses {
+    const double *xy;
+    __device__ bool operator()(int64_t q, int64_t &k, double &X, double &Y) const {
+        k = q;
+        X = ((global_double *)xy)[2 * q];
+        Y = ((global_double *)xy)[2 * q + 1];
+        return true;
+    }
+};
+
+// Records of super-patch sp from every lens (the mixed mode's re-check stage,
+// random rays and batches): far lenses -> coefficients about zS; the others ->
+// the super-patch's lens list.
+template <bool UNIT>
+__device__ __forceinline__ void build_super(const ShootArgs &a, int64_t sp, FarSuperSmem &sm) {
+    double cx, cy, H;
+    super_geometry(a, sp, cx, cy, H);
+    build_level<UNIT>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy}, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
+                      a.ff_super + sp * (int64_t)FAR_REC, nullptr, 0.0, 0.0, sm);
 }
 
 // Level 1 of one launch (or, for random rays, of the whole rectangle): one block
@@ -164,6 +217,83 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const Shoot
     __shared__ FarSuperSmem sm;
     if (RECHECK && *a.qcount == 0) return;
     build_super<UNIT>(a, blockIdx.x, sm);
+}
+
+// Far-field mode, level 0: groups of FF_GROUP x FF_GROUP super-patches (centre
+// zG, half-diagonal HG, one ray spacing of slack on each side, of the full box).
+__device__ __forceinline__ void group_geometry(const ShootArgs &a, int64_t g, double &cx, double &cy, double &H) {
+    constexpr int GX = FF_GROUP * FF_SP_X * PATCH_X, GY = FF_GROUP * FF_SP_Y * PATCH_Y;
+    const int64_t gx = g % a.ff_gbx, gy = g / a.ff_gbx;
+    const int64_t i_g = a.ff_i0 + gx * GX;
+    const int64_t j_g = a.ff_j0 + gy * GY;
+    cx = a.sx0 + ((double)i_g + 0.5 * GX) * a.spx;
+    cy = a.sy0 + ((double)j_g + 0.5 * GY) * a.spy;
+    const double hx = (0.5 * GX + 1.0) * a.spx;
+    const double hy = (0.5 * GY + 1.0) * a.spy;
+    H = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
+}
+
+__device__ __forceinline__ int64_t group_of(const ShootArgs &a, int64_t sp) {
+    return ((sp / a.ff_sbx) / FF_GROUP) * a.ff_gbx + (sp % a.ff_sbx) / FF_GROUP;
+}
+
+// A level's candidates from the list of the level above (centre (cx, cy),
+// radius FAR_RATIO H), or, when that list overflowed, every lens that level
+// did not expand (the same test it made).
+struct ListCandidates {
+    const double *xy;
+    const global_i32 *list;
+    bool scan_all;
+    double cx, cy, r2;
+    __device__ bool operator()(int64_t q, int64_t &k, double &X, double &Y) const {
+        k = scan_all ? q : (int64_t)list[1 + q];
+        X = ((global_double *)xy)[2 * k];
+        Y = ((global_double *)xy)[2 * k + 1];
+        if (scan_all) {
+            const double e1 = cx - X, e2 = cy - Y;
+            if (e1 * e1 + e2 * e2 >= r2) return false;
+        }
+        return true;
+    }
+};
+
+__device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, int64_t g, int64_t &n) {
+    ListCandidates c;
+    c.xy = a.lens_xy;
+    double H;
+    group_geometry(a, g, c.cx, c.cy, H);
+    c.r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
+    c.list = (const global_i32 *)(a.ff_glist + g * (int64_t)(1 + FF_GROUP_CAP));
+    const int32_t listed = c.list[0];
+    c.scan_all = listed > FF_GROUP_CAP;
+    n = c.scan_all ? a.n_lens : listed;
+    return c;
+}
+
+// Far-field mode, level 0: one block per group, every lens.
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_group_kernel(const ShootArgs a) {
+    __shared__ FarSuperSmem sm;
+    const int64_t g = blockIdx.x;
+    double cx, cy, H;
+    group_geometry(a, g, cx, cy, H);
+    build_level<UNIT>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy}, a.ff_glist + g * (int64_t)(1 + FF_GROUP_CAP),
+                      FF_GROUP_CAP, a.ff_group + g * (int64_t)FAR_REC, nullptr, 0.0, 0.0, sm);
+}
+
+// Far-field mode, level 1: one block per super-patch, candidates from its group,
+// the group's expansion re-centred and added.
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_THREADS) void farfield_super_group_kernel(const ShootArgs a) {
+    __shared__ FarSuperSmem sm;
+    const int64_t sp = blockIdx.x;
+    const int64_t g = group_of(a, sp);
+    int64_t n;
+    const ListCandidates c = group_candidates(a, g, n);
+    double cx, cy, H;
+    super_geometry(a, sp, cx, cy, H);
+    build_level<UNIT>(a, cx, cy, H, n, c, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
+                      a.ff_super + sp * (int64_t)FAR_REC, a.ff_group + g * (int64_t)FAR_REC, c.cx, c.cy, sm);
 }
 
 // Level 1 of every map of a mixed batch that flagged rays: one block per
@@ -210,13 +340,14 @@ __device__ __forceinline__ PatchFrame patch_frame(const ShootArgs &a, int64_t pa
 }
 
 // The candidates of a patch: the super-patch's list, or, when that list
-// overflowed, every lens the super-patch did not expand (the same test the
-// super kernel made). Calls visit(k, X, Y) for candidate q of n.
+// overflowed, every lens that neither its group nor the super-patch expanded
+// (the same tests those levels made).
 struct Candidates {
     const global_i32 *list;
     int64_t n;
     bool scan_all;
     double cx, cy, super_r2;
+    double gx, gy, group_r2;
 };
 
 __device__ __forceinline__ Candidates candidates(const ShootArgs &a, int64_t sp) {
@@ -228,17 +359,21 @@ __device__ __forceinline__ Candidates candidates(const ShootArgs &a, int64_t sp)
     const int32_t listed = c.list[0];
     c.scan_all = listed > a.ff_cap;
     c.n = c.scan_all ? a.n_lens : listed;
+    group_geometry(a, group_of(a, sp), c.gx, c.gy, H);
+    c.group_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
     return c;
 }
 
 // Candidate q: its lens index and position; false when an overflowed list's
-// scan meets a lens the super-patch expanded.
+// scan meets a lens a level above expanded.
 __device__ __forceinline__ bool candidate(const ShootArgs &a, const Candidates &c, int64_t q, int64_t &k, double &X,
                                           double &Y) {
     k = c.scan_all ? q : (int64_t)c.list[1 + q];
     X = ((global_double *)a.lens_xy)[2 * k];
     Y = ((global_double *)a.lens_xy)[2 * k + 1];
     if (c.scan_all) {
+        const double f1 = c.gx - X, f2 = c.gy - Y;
+        if (f1 * f1 + f2 * f2 >= c.group_r2) return false;
         const double e1 = c.cx - X, e2 = c.cy - Y;
         if (e1 * e1 + e2 * e2 >= c.super_r2) return false;
     }
@@ -249,32 +384,51 @@ __device__ __forceinline__ bool candidate(const ShootArgs &a, const Candidates &
 // farther than FAR_RATIO h from the patch centre add their own expansion about
 // it; the super-patch expansion is re-centred exactly on it,
 //   sum_n C_n (e + v)^n = sum_m v^m sum_{n>=m} binom(n, m) e^(n-m) C_n,
-// v = -w = z0 - z, e = zS - z0; the record holds the sum of both and the bound
-// terms of both levels (truncation, and rounding of the coefficients, the
-// translation and the evaluation, with per-level factors and generous constants).
+// v = -w = z0 - z, e = zS - z0; the record holds the sum of both, the bound terms
+// of both levels (truncation, and rounding of the coefficients, the translation
+// and the evaluation, with per-level factors and generous constants), and the
+// nearer candidates, in candidate order, for the ray kernel's direct sum. Block 0
+// also resets the ray kernel's patch counter.
 template <bool UNIT>
 __global__ __launch_bounds__(FAR_THREADS) void farfield_patch_kernel(const ShootArgs a, int64_t patches) {
     constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.ff_work = 0u;
     const int lane = threadIdx.x & 63;
     const int64_t patch = (int64_t)blockIdx.x * (FAR_THREADS / 64) + (threadIdx.x >> 6);
     if (patch >= patches) return;   // the whole wave
     const PatchFrame f = patch_frame(a, patch);
     const Candidates c = candidates(a, f.sp);
+    double *rec = a.ff_patch + patch * (int64_t)FF_PATCH_DOUBLES;
     FarAcc acc;
     acc.zero();
-    for (int64_t q = lane; q < c.n; q += 64) {
-        int64_t k;
-        double X, Y;
-        if (!candidate(a, c, q, k, X, Y)) continue;
-        const double d1 = f.ox - X, d2 = f.oy - Y;
-        const double r2 = d1 * d1 + d2 * d2;
-        if (!(r2 >= f.near_r2)) continue;   // summed directly by the ray kernel
-        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
-        acc.add(d1, d2, r2, m, f.h);
+    int n_near = 0;
+    for (int64_t q0 = 0; q0 < c.n; q0 += 64) {
+        const int64_t q = q0 + lane;
+        int64_t k = 0;
+        double X = 0.0, Y = 0.0, m = 1.0, d1 = 0.0, d2 = 0.0, r2 = 0.0;
+        bool is_far = false, is_near = false;
+        if (q < c.n && candidate(a, c, q, k, X, Y)) {
+            d1 = f.ox - X;
+            d2 = f.oy - Y;
+            r2 = d1 * d1 + d2 * d2;
+            m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
+            is_far = r2 >= f.near_r2;
+            is_near = !is_far;
+        }
+        if (is_far) acc.add(d1, d2, r2, m, f.h);
+        const uint64_t nb = __ballot(is_near);
+        if (is_near) {
+            const int pos = n_near + __builtin_popcountll(nb & ((1ull << lane) - 1ull));
+            if (pos < FF_PATCH_NEAR) {
+                rec[FF_PATCH_HEAD + pos] = X;
+                rec[FF_PATCH_HEAD + FF_PATCH_NEAR + pos] = Y;
+                rec[FF_PATCH_HEAD + 2 * FF_PATCH_NEAR + pos] = m;
+            }
+        }
+        n_near += __builtin_popcountll(nb);
     }
     acc.butterfly();   // every lane now holds the wave's sums
     const global_double *sc = (const global_double *)(a.ff_super + f.sp * (int64_t)FAR_REC);
-    double *rec = a.ff_patch + patch * (int64_t)FF_PATCH_DOUBLES;
     if (lane < FAR_P) {
         const int mm = lane;
         double p1 = 0.0, p2 = 0.0;
@@ -285,9 +439,7 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_patch_kernel(const Shoot
                 p2 = acc.c2[n];
             }
         }
-        double cx, cy, H;
-        super_geometry(a, f.sp, cx, cy, H);
-        const double e1 = cx - f.ox, e2 = cy - f.oy;
+        const double e1 = c.cx - f.ox, e2 = c.cy - f.oy;
         double s1 = 0.0, s2 = 0.0;
         double g1 = 1.0, g2 = 0.0;   // e^(n-m)
         for (int n = mm; n < FAR_P; ++n) {
@@ -308,157 +460,174 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_patch_kernel(const Shoot
         rec[2 * FAR_P + 1] = TRUNC_S + acc.trunc + (NFAR_S + 24.0 * FAR_P + 64.0) * U64 * 1.34 * SFAR_S +
                              (acc.nfar + 16.0 * FAR_P + 64.0) * U64 * 1.34 * acc.sfar;
         rec[2 * FAR_P + 2] = SDEF_S + acc.sdef;
-        rec[2 * FAR_P + 3] = 0.0;
+        rec[2 * FAR_P + 3] = (double)n_near;
+    } else if (lane <= FAR_P + FF_PATCH_HEAD - (2 * FAR_P + 4)) {
+        rec[2 * FAR_P + 4 + (lane - FAR_P - 1)] = 0.0;   // the spare doubles
     }
 }
 
 struct FarSmem {
     PixelTable table;            // the patch's counts per pixel (map mode)
     double near_x[NEAR_EXP], near_y[NEAR_EXP], near_m[NEAR_EXP];
-    double rec[FF_PATCH_DOUBLES];
-    unsigned long long n_in, n_out;
-    int near_count;
+    double rec[FF_PATCH_HEAD];
+    int near_count[2];           // by patch parity: one is filled while the other is cleared
+    int next;                    // the patch after this one
 };
 
-// Level 2, part 2: the rays, one block per patch. The patch's near lenses go to
-// LDS (beyond NEAR_EXP of them the patch is re-checked whole); each thread then
-// takes 8 rays: the series (Horner in v), the near lenses directly, the pixel
-// decision against the bound, the count.
+// Level 2, part 2: the rays. Persistent blocks take patches from a counter. A
+// patch's near lenses come from its record, or, when the record could not hold
+// them all, from the candidates with the record kernel's test (beyond NEAR_EXP
+// of them the patch is re-checked whole). Each thread then takes 8 rays: the
+// series (Horner in v), the near lenses directly, the pixel decision against the
+// bound, and the count in the block's pixel table, which is added to the map
+// (one global atomic per distinct pixel) and cleared after every patch.
 template <bool UNIT, bool PIX>
-__global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArgs a) {
+__global__ __launch_bounds__(FAR_THREADS, 3) void farfield_kernel(const ShootArgs a, int64_t patches) {
     __shared__ FarSmem sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t patch = blockIdx.x;
-    const PatchFrame f = patch_frame(a, patch);
-    const int64_t ib = f.ib, jb = f.jb;
-    const double ox = f.ox, oy = f.oy;
-    const Candidates c = candidates(a, f.sp);
-    if (tid == 0) {
-        sm.near_count = 0;
-        sm.n_in = 0;
-        sm.n_out = 0;
-    }
-    if (tid < FF_PATCH_DOUBLES)
-        sm.rec[tid] = ((const global_double *)a.ff_patch)[patch * (int64_t)FF_PATCH_DOUBLES + tid];
     if (!PIX) table_clear<FAR_THREADS>(sm.table, tid);
-    __syncthreads();
-    for (int64_t q = tid; q < c.n; q += FAR_THREADS) {
-        int64_t k;
-        double X, Y;
-        if (!candidate(a, c, q, k, X, Y)) continue;
-        const double d1 = ox - X, d2 = oy - Y;
-        const double r2 = d1 * d1 + d2 * d2;
-        if (r2 >= f.near_r2) continue;   // in the patch's expansion
-        const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
-        const int j = atomicAdd(&sm.near_count, 1);
-        if (j < NEAR_EXP) {
-            sm.near_x[j] = X;
-            sm.near_y[j] = Y;
-            sm.near_m[j] = m;
-        }
+    if (tid == 0) {
+        sm.near_count[0] = 0;
+        sm.near_count[1] = 0;
+        sm.next = (int)atomicAdd(a.ff_work, 1u);
     }
     __syncthreads();
-    const double SFAR = sm.rec[2 * FAR_P], far_err = sm.rec[2 * FAR_P + 1], SDEF = sm.rec[2 * FAR_P + 2];
-    const int n_near_all = sm.near_count;
-    const bool all_flagged = n_near_all > NEAR_EXP;
-    const int n_near = all_flagged ? 0 : n_near_all;
-
+    int64_t patch = sm.next;
     unsigned long long n_in = 0, n_out = 0;
     const int64_t W = a.i1 - a.i0;
-    // A wave takes 8 x 8-ray blocks of the patch (block wave + 4 r, r < 8), so the
-    // rays of one wave land on few pixels. Ray r of this thread has column
-    // ib + 8 ((wave + 4 r) % 8) + lane % 8 (two values, r even or odd) and row
-    // jb + 8 (r / 2) + lane / 8 (four values).
-    const int wave = tid >> 6;
-    auto col = [&](int c) { return ib + 8 * ((wave + 4 * c) % (PATCH_X / 8)) + (lane & 7); };
-    auto row = [&](int rr) { return jb + 8 * rr + (lane >> 3); };
-    double X1[2], X2[FAR_ROWS / 2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) X1[c] = ray_coord(a.sx0, col(c), a.spx);
-#pragma unroll
-    for (int rr = 0; rr < FAR_ROWS / 2; ++rr) X2[rr] = ray_coord(a.sy0, row(rr), a.spy);
-    // The thread's rays in two passes of RPASS: per pass, (1) the expansion of each
-    // ray (independent Horner chains), (2) the near lenses, each read from LDS once
-    // per pass and added onto each ray's far part in list order, (3) the pixel
-    // decision and binning into the block's pixel table.
-    constexpr int RPASS = FAR_ROWS / 2;
-#pragma unroll
-    for (int pass = 0; pass < FAR_ROWS / RPASS; ++pass) {
-        double A1[RPASS], A2[RPASS];
-        {
-            double T1[FAR_P], T2[FAR_P];
-#pragma unroll
-            for (int n = 0; n < FAR_P; ++n) {
-                T1[n] = sm.rec[n];
-                T2[n] = sm.rec[FAR_P + n];
+    for (int par = 0; patch < patches; par ^= 1) {
+        uint32_t next = 0;
+        if (tid == 0) next = atomicAdd(a.ff_work, 1u);   // used after the rays: its latency is hidden
+        const PatchFrame f = patch_frame(a, patch);
+        const int64_t ib = f.ib, jb = f.jb;
+        const double ox = f.ox, oy = f.oy;
+        const global_double *R = (const global_double *)(a.ff_patch + patch * (int64_t)FF_PATCH_DOUBLES);
+        if (tid < FF_PATCH_HEAD) sm.rec[tid] = R[tid];
+        const int stored = (int)R[2 * FAR_P + 3];
+        if (stored <= FF_PATCH_NEAR) {
+            if (tid < stored) {
+                sm.near_x[tid] = R[FF_PATCH_HEAD + tid];
+                sm.near_y[tid] = R[FF_PATCH_HEAD + FF_PATCH_NEAR + tid];
+                sm.near_m[tid] = R[FF_PATCH_HEAD + 2 * FF_PATCH_NEAR + tid];
             }
-#pragma unroll
-            for (int k = 0; k < RPASS; ++k) {
-                const int r = pass * RPASS + k;
-                const double nw1 = ox - X1[r & 1], nw2 = oy - X2[r >> 1];   // -w
-                double S1 = T1[FAR_P - 1], S2 = T2[FAR_P - 1];
-#pragma unroll
-                for (int n = FAR_P - 2; n >= 0; --n) {
-                    const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, T1[n]));
-                    const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, T2[n]));
-                    S1 = q1;
-                    S2 = q2;
+            if (tid == 0) sm.near_count[par] = stored;
+        } else {
+            const Candidates c = candidates(a, f.sp);
+            for (int64_t q = tid; q < c.n; q += FAR_THREADS) {
+                int64_t k;
+                double X, Y;
+                if (!candidate(a, c, q, k, X, Y)) continue;
+                const double d1 = ox - X, d2 = oy - Y;
+                const double r2 = d1 * d1 + d2 * d2;
+                if (r2 >= f.near_r2) continue;   // in the patch's expansion
+                const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
+                const int j = atomicAdd(&sm.near_count[par], 1);
+                if (j < NEAR_EXP) {
+                    sm.near_x[j] = X;
+                    sm.near_y[j] = Y;
+                    sm.near_m[j] = m;
                 }
-                A1[k] = S1;
-                A2[k] = -S2;
             }
         }
-        double SN[RPASS];
+        __syncthreads();
+        const double SFAR = sm.rec[2 * FAR_P], far_err = sm.rec[2 * FAR_P + 1], SDEF = sm.rec[2 * FAR_P + 2];
+        const int n_near_all = sm.near_count[par];
+        if (tid == 0) sm.near_count[par ^ 1] = 0;   // every thread read it one patch ago
+        const bool all_flagged = n_near_all > NEAR_EXP;
+        const int n_near = all_flagged ? 0 : n_near_all;
+
+        // A wave takes 8 x 8-ray blocks of the patch (block wave + 4 r, r < 8), so the
+        // rays of one wave land on few pixels. Ray r of this thread has column
+        // ib + 8 ((wave + 4 r) % 8) + lane % 8 (two values, r even or odd) and row
+        // jb + 8 (r / 2) + lane / 8 (four values).
+        const int wave = tid >> 6;
+        auto col = [&](int c) { return ib + 8 * ((wave + 4 * c) % (PATCH_X / 8)) + (lane & 7); };
+        auto row = [&](int rr) { return jb + 8 * rr + (lane >> 3); };
+        double X1[2], X2[FAR_ROWS / 2];
 #pragma unroll
-        for (int k = 0; k < RPASS; ++k) SN[k] = 0.0;
-        uint32_t tiny = 0u;
-        for (int q = 0; q < n_near; ++q) {
-            const double X = sm.near_x[q], Y = sm.near_y[q], M = sm.near_m[q];
+        for (int c = 0; c < 2; ++c) X1[c] = ray_coord(a.sx0, col(c), a.spx);
+#pragma unroll
+        for (int rr = 0; rr < FAR_ROWS / 2; ++rr) X2[rr] = ray_coord(a.sy0, row(rr), a.spy);
+        // The thread's rays in two passes of RPASS: per pass, (1) the expansion of each
+        // ray (independent Horner chains), (2) the near lenses, each read from LDS once
+        // per pass and added onto each ray's far part in list order, (3) the pixel
+        // decision and binning into the block's pixel table.
+        constexpr int RPASS = FAR_ROWS / 2;
+#pragma unroll
+        for (int pass = 0; pass < FAR_ROWS / RPASS; ++pass) {
+            double A1[RPASS], A2[RPASS];
+            {
+                double T1[FAR_P], T2[FAR_P];
+#pragma unroll
+                for (int n = 0; n < FAR_P; ++n) {
+                    T1[n] = sm.rec[n];
+                    T2[n] = sm.rec[FAR_P + n];
+                }
+#pragma unroll
+                for (int k = 0; k < RPASS; ++k) {
+                    const int r = pass * RPASS + k;
+                    const double nw1 = ox - X1[r & 1], nw2 = oy - X2[r >> 1];   // -w
+                    double S1 = T1[FAR_P - 1], S2 = T2[FAR_P - 1];
+#pragma unroll
+                    for (int n = FAR_P - 2; n >= 0; --n) {
+                        const double q1 = __builtin_fma(S1, nw1, __builtin_fma(-S2, nw2, T1[n]));
+                        const double q2 = __builtin_fma(S1, nw2, __builtin_fma(S2, nw1, T2[n]));
+                        S1 = q1;
+                        S2 = q2;
+                    }
+                    A1[k] = S1;
+                    A2[k] = -S2;
+                }
+            }
+            double SN[RPASS];
+#pragma unroll
+            for (int k = 0; k < RPASS; ++k) SN[k] = 0.0;
+            uint32_t tiny = 0u;
+            for (int q = 0; q < n_near; ++q) {
+                const double X = sm.near_x[q], Y = sm.near_y[q], M = sm.near_m[q];
+#pragma unroll
+                for (int k = 0; k < RPASS; ++k) {
+                    const int r = pass * RPASS + k;
+                    const double e1 = X1[r & 1] - X, e2 = X2[r >> 1] - Y;
+                    const double r2 = __builtin_fma(e1, e1, e2 * e2);
+                    if (!(r2 > 1e-200)) tiny |= 1u << k;
+                    const double f = M * rcp64(r2);
+                    A1[k] = __builtin_fma(f, e1, A1[k]);
+                    A2[k] = __builtin_fma(f, e2, A2[k]);
+                    SN[k] = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), SN[k]);
+                }
+            }
 #pragma unroll
             for (int k = 0; k < RPASS; ++k) {
                 const int r = pass * RPASS + k;
-                const double e1 = X1[r & 1] - X, e2 = X2[r >> 1] - Y;
-                const double r2 = __builtin_fma(e1, e1, e2 * e2);
-                if (!(r2 > 1e-200)) tiny |= 1u << k;
-                const double f = M * rcp64(r2);
-                A1[k] = __builtin_fma(f, e1, A1[k]);
-                A2[k] = __builtin_fma(f, e2, A2[k]);
-                SN[k] = __builtin_fma(fabs(e1) + fabs(e2), fabs(f), SN[k]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < RPASS; ++k) {
-            const int r = pass * RPASS + k;
-            const int64_t i = col(r & 1), j = row(r >> 1);
-            const bool valid = (i < a.i1) && (j < a.jc1);
-            int code = far_decide(a, X1[r & 1], X2[r >> 1], A1[k], A2[k], far_err, SFAR, SDEF, SN[k], n_near,
-                                  !((tiny >> k) & 1u) && !all_flagged);
-            if (!valid) code = INT32_MIN;
+                const int64_t i = col(r & 1), j = row(r >> 1);
+                const bool valid = (i < a.i1) && (j < a.jc1);
+                int code = far_decide(a, X1[r & 1], X2[r >> 1], A1[k], A2[k], far_err, SFAR, SDEF, SN[k], n_near,
+                                      !((tiny >> k) & 1u) && !all_flagged);
+                if (!valid) code = INT32_MIN;
 
-            n_in += __builtin_popcountll(__ballot(code >= 0));
-            n_out += __builtin_popcountll(__ballot(code == OUT));
-            if (PIX) {
-                if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
-            } else {
-                table_add(sm.table, a.map, code);
+                n_in += __builtin_popcountll(__ballot(code >= 0));
+                n_out += __builtin_popcountll(__ballot(code == OUT));
+                if (PIX) {
+                    if (valid && code != FLAGGED) a.pix_out[(j - a.j0) * W + (i - a.i0)] = code;
+                } else {
+                    table_add(sm.table, a.map, code);
+                }
+                const uint64_t fl = __ballot(code == FLAGGED);
+                if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
             }
-            const uint64_t fl = __ballot(code == FLAGGED);
-            if (fl) SingleSink{}.append(a, fl, lane, code == FLAGGED, i, j);
         }
+        if (tid == 0) sm.next = (int)next;
+        __syncthreads();   // every ray of the patch is in the table
+        if (!PIX) table_flush_clear<FAR_THREADS>(sm.table, a.map, tid);
+        patch = sm.next;
     }
     if (lane == 0) {
-        if (n_in) atomicAdd(&sm.n_in, n_in);
-        if (n_out) atomicAdd(&sm.n_out, n_out);
-    }
-    __syncthreads();   // every ray of the patch is in the table and the block's counts
-    if (!PIX) table_flush<FAR_THREADS>(sm.table, a.map, tid);
-    if (tid == 0) {
-        if (sm.n_in) global_add(a.counters + C_IN, sm.n_in);
-        if (sm.n_out) global_add(a.counters + C_OUT, sm.n_out);
+        if (n_in) global_add(a.counters + C_IN, n_in);
+        if (n_out) global_add(a.counters + C_OUT, n_out);
     }
 }
-
 
 // Re-check stage of the mixed mode on the regular grid, one thread per queued
 // ray (far_recheck_ray). A ray it places is binned and its entry marked
@@ -545,22 +714,31 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     const bool unit = a.lens_m == nullptr;
     const bool pix = a.pix_out != nullptr;
     const dim3 block(FAR_THREADS);
-    if (unit) hipLaunchKernelGGL((farfield_super_kernel<true, false>), dim3((unsigned)n_super), block, 0, stream, a);
-    else hipLaunchKernelGGL((farfield_super_kernel<false, false>), dim3((unsigned)n_super), block, 0, stream, a);
+    const int64_t n_group = a.ff_gbx * ((((nby + FF_SP_Y - 1) / FF_SP_Y) + FF_GROUP - 1) / FF_GROUP);
+    if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), dim3((unsigned)n_group), block, 0, stream, a);
+    else hipLaunchKernelGGL((farfield_group_kernel<false>), dim3((unsigned)n_group), block, 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (unit) hipLaunchKernelGGL((farfield_super_group_kernel<true>), dim3((unsigned)n_super), block, 0, stream, a);
+    else hipLaunchKernelGGL((farfield_super_group_kernel<false>), dim3((unsigned)n_super), block, 0, stream, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 rec_grid((unsigned)((patches + FAR_THREADS / 64 - 1) / (FAR_THREADS / 64)));
     if (unit) hipLaunchKernelGGL((farfield_patch_kernel<true>), rec_grid, block, 0, stream, a, patches);
     else hipLaunchKernelGGL((farfield_patch_kernel<false>), rec_grid, block, 0, stream, a, patches);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)patches);
+    auto launch_rays = [&](auto kernel) {
+        int64_t blocks = persistent_blocks(kernel, FAR_THREADS, 0);
+        if (blocks > patches) blocks = patches;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), block, 0, stream, a, patches);
+    };
     if (unit) {
-        if (pix) hipLaunchKernelGGL((farfield_kernel<true, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((farfield_kernel<true, false>), grid, block, 0, stream, a);
+        if (pix) launch_rays(farfield_kernel<true, true>);
+        else launch_rays(farfield_kernel<true, false>);
     } else {
-        if (pix) hipLaunchKernelGGL((farfield_kernel<false, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((farfield_kernel<false, false>), grid, block, 0, stream, a);
+        if (pix) launch_rays(farfield_kernel<false, true>);
+        else launch_rays(farfield_kernel<false, false>);
     }
     return hipGetLastError();
 }

@@ -65,6 +65,10 @@ struct ShootArgs {
     int32_t *ff_near;      // [n_super][1 + ff_cap] count, then indices of the nearer lenses
     int32_t ff_cap;        // list capacity per super-patch
     double *ff_patch;      // far-field mode: [patches of the launch][FF_PATCH_DOUBLES] patch records
+    uint32_t *ff_work;     // far-field mode: next patch to take (reset by the record kernel)
+    int64_t ff_gbx;        // far-field mode: groups (FF_GROUP x FF_GROUP super-patches) along x
+    double *ff_group;      // far-field mode: [groups][FF_REC_DOUBLES] group records
+    int32_t *ff_glist;     // far-field mode: [groups][1 + FF_GROUP_CAP] count, then the nearer lenses
 };
 
 
@@ -226,6 +230,21 @@ inline int64_t bitmap_words_of(const rs_map_params &p) {
     const int64_t rays = (p.i1 - p.i0) * (p.j1 - p.j0);
     const int64_t words = (rays + 31) / 32;
     return (words + BITMAP_WORD_ALIGN - 1) / BITMAP_WORD_ALIGN * BITMAP_WORD_ALIGN;
+}
+
+// Blocks of a persistent kernel on the current device: every CU times
+// min(blocks_per_cu, the blocks that fit on it); blocks_per_cu <= 0 takes all that fit.
+template <class K>
+inline int persistent_blocks(K kernel, int threads, int blocks_per_cu) {
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+        n_cu = 256;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 2;
+    if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
+    return n_cu * per_cu;
 }
 
 hipError_t launch_fill(uint32_t *map, int64_t n_pix, void *workspace, int64_t n_qcount,

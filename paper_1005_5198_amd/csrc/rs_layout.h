@@ -35,10 +35,18 @@ constexpr int FF_SP_Y = 4;
 constexpr int FF_NEAR_CAP = 4096;    // single maps (the far-field mode rescans all lenses beyond it)
 constexpr int FF_BATCH_CAP = 1024;   // batches (the re-check stage only; beyond it, the stage over every lens)
 constexpr int FF_REC_DOUBLES = 36;
+// Far-field mode: groups of FF_GROUP x FF_GROUP super-patches above the
+// super-patches (their lists hold the candidates of their super-patches).
+constexpr int FF_GROUP = 4;
+constexpr int FF_GROUP_CAP = 16384;
 // Far-field mode, per 64 x 32-ray patch: the local expansion about the patch
-// centre (16 real, 16 imaginary coefficients), then the bound terms SFAR, far_err
-// and SDEF, and one spare double.
-constexpr int FF_PATCH_DOUBLES = 36;
+// centre (16 real, 16 imaginary coefficients), the bound terms SFAR, far_err and
+// SDEF, the number of near lenses (summed directly), three spare doubles, then
+// the first FF_PATCH_NEAR near lenses' x, y and mass (when there are more, the
+// ray kernel finds them itself).
+constexpr int FF_PATCH_HEAD = 40;
+constexpr int FF_PATCH_NEAR = 24;
+constexpr int FF_PATCH_DOUBLES = FF_PATCH_HEAD + 3 * FF_PATCH_NEAR;
 
 // Random rays: expected rays per bin (a block's capacity is 2048, so a bin
 // overflows it only beyond three standard deviations, about one bin in 3000,

@@ -29,9 +29,13 @@ struct Plan {
     // Far-field expansion: super-patch records and lens lists for the largest launch.
     int64_t super_cap = 0;
     size_t ff_super_off = 0, ff_near_off = 0;
-    // Far-field mode: the patch records of the largest launch.
+    // Far-field mode: the patch records of the largest launch, and the counter
+    // from which the ray kernel's blocks take patches.
     int64_t patch_cap = 0;
-    size_t ff_patch_off = 0;
+    size_t ff_patch_off = 0, ff_work_off = 0;
+    // Far-field mode: group records and lists of the largest launch.
+    int64_t group_cap = 0;
+    size_t ff_group_off = 0, ff_glist_off = 0;
     size_t bytes = 0;
 };
 

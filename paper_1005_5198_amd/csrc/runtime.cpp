@@ -242,7 +242,13 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
         a.ff_super = reinterpret_cast<double *>(ws + pl.ff_super_off);
         a.ff_near = reinterpret_cast<int32_t *>(ws + pl.ff_near_off);
         a.ff_cap = FF_NEAR_CAP;
-        if (p->mode == RS_FARFIELD) a.ff_patch = reinterpret_cast<double *>(ws + pl.ff_patch_off);
+        if (p->mode == RS_FARFIELD) {
+            a.ff_patch = reinterpret_cast<double *>(ws + pl.ff_patch_off);
+            a.ff_work = reinterpret_cast<uint32_t *>(ws + pl.ff_work_off);
+            a.ff_gbx = (a.ff_sbx + FF_GROUP - 1) / FF_GROUP;
+            a.ff_group = reinterpret_cast<double *>(ws + pl.ff_group_off);
+            a.ff_glist = reinterpret_cast<int32_t *>(ws + pl.ff_glist_off);
+        }
         if (pl.random) {
             a.ff_i0 = 0;
             a.ff_j0 = 0;

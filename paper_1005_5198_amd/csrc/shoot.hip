@@ -418,30 +418,11 @@ static void launch_shape(const ShootArgs &a, int mode, dim3 grid, hipStream_t st
     }
 #undef RS_LAUNCH
 }
-
 const ShapeInfo &shape_info(int shape) {
     static const ShapeInfo table[N_SHAPES] = {
         {4, 2, 2, 2}, {4, 4, 2, 1}, {8, 2, 1, 2}, {8, 4, 1, 1},
     };
     return table[(shape >= 0 && shape < N_SHAPES) ? shape : 0];
-}
-
-// Blocks of a persistent kernel: every CU times min(blocks_per_cu, the blocks that
-// fit on it); blocks_per_cu <= 0 takes all that fit.
-template <class K>
-static int persistent_blocks(K kernel, int threads, int blocks_per_cu) {
-    static int n_cu = 0;
-    if (n_cu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
-            n_cu = 256;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
-        per_cu = 2;
-    if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
-    return n_cu * per_cu;
 }
 
 template <int RX, int RY, int WX, int WY, bool UNIT, int MODE>

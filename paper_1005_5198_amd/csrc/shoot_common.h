@@ -109,9 +109,12 @@ __device__ __forceinline__ void table_add(PixelTable &t, uint32_t *map, int p) {
 }
 static_assert(PT_SLOTS == 1 << 11, "the hash keeps 11 bits");
 
-// All slots' counts and keys are read before the first global atomic is issued.
+// Adds every used slot's count to the map and empties the slot (a slot holds a
+// key exactly when its count is positive). All slots' counts and keys are read
+// before the first global atomic is issued. The caller separates this from the
+// table's last and next use by barriers.
 template <int THREADS>
-__device__ __forceinline__ void table_flush(const PixelTable &t, uint32_t *map, int tid) {
+__device__ __forceinline__ void table_flush_clear(PixelTable &t, uint32_t *map, int tid) {
     static_assert(PT_SLOTS % THREADS == 0, "whole rounds of slots");
     constexpr int R = PT_SLOTS / THREADS;
     uint32_t c[R], k[R];
@@ -121,8 +124,13 @@ __device__ __forceinline__ void table_flush(const PixelTable &t, uint32_t *map, 
         k[r] = t.key[tid + r * THREADS];
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (c[r]) global_add(map + (k[r] - 1u), c[r]);
+    for (int r = 0; r < R; ++r) {
+        if (c[r]) {
+            t.cnt[tid + r * THREADS] = 0u;
+            t.key[tid + r * THREADS] = 0u;
+            global_add(map + (k[r] - 1u), c[r]);
+        }
+    }
 }
 
 struct ShootSmem {
