@@ -65,7 +65,7 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
     pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
     const int64_t rows_cap = pl.H < rows ? pl.H : rows;
     pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
-    pl.qcount_bytes = (WS_QCOUNT + 12 * (size_t)pl.n_chunks + 255) / 256 * 256;
+    pl.qcount_bytes = (WS_QCOUNT + 12 * (size_t)pl.n_chunks + 4 + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
     pl.far_recheck = p->mode == RS_MIXED && !(p->flags & RS_EXACT_RECHECK);
     if (pl.far_recheck && pl.random) {
@@ -100,6 +100,11 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
             off += a256(sizeof(int32_t) * (1 + (size_t)FF_GROUP_CAP) * (size_t)pl.group_cap);
         }
         pl.bytes = off;
+    }
+    if (p->mode != RS_FP32 && !(p->flags & RS_EXACT_RECHECK) && pl.n_chunks > 1) {
+        pl.defer = true;
+        pl.defer_off = a256(pl.bytes);
+        pl.bytes = pl.defer_off + sizeof(int64_t) * 2 * (size_t)DEFER_CAP;
     }
     if (pl.random && pl.n_chunks > 0) {
         pl.rays_cap = rows_cap * pl.W;

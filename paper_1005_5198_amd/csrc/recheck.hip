@@ -177,6 +177,44 @@ __global__ __launch_bounds__(256) void recheck_exact_wave_kernel(const RecheckAr
     }
 }
 
+// Maps of several launches: after stage A, the entries it left go to the map's
+// deferred list (their marks cleared, the launch's unresolved count lowered), so
+// the exact stage, whose cost is one pass over every lens whatever the number of
+// rays, runs once per map instead of once per launch. Entries beyond the list's
+// capacity stay marked for their launch's exact stage.
+__global__ __launch_bounds__(256) void recheck_defer_kernel(const RecheckArgs a) {
+    if (*a.qunres == 0u) return;
+    const uint32_t n = *a.qcount;
+    const int64_t W = a.i1 - a.i0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        const uint32_t q = a.queue[idx];
+        if (!(q & UNRESOLVED)) continue;
+        const uint32_t d = atomicAdd(a.dcount, 1u);
+        if (d >= (uint32_t)DEFER_CAP) continue;
+        const uint32_t rel = q & ~UNRESOLVED;
+        a.defer[2 * (int64_t)d] = a.i0 + (int64_t)(rel % (uint64_t)W);
+        a.defer[2 * (int64_t)d + 1] = a.jc0 + (int64_t)(rel / (uint64_t)W);
+        a.queue[idx] = rel;
+        atomicSub(a.qunres, 1u);
+    }
+}
+
+// The exact stage over a map's deferred list, one wave per ray.
+template <bool UNIT>
+__global__ __launch_bounds__(256) void recheck_exact_deferred_kernel(const RecheckArgs a) {
+    const uint32_t total = *a.dcount;
+    const uint32_t n = total < (uint32_t)DEFER_CAP ? total : (uint32_t)DEFER_CAP;
+    const int lane = __lane_id();
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t e = wave_id; e < n; e += n_waves) {
+        const int64_t i = a.defer[2 * (int64_t)e], j = a.defer[2 * (int64_t)e + 1];
+        const int code = exact_ray_wave<UNIT>(a, i, j);
+        if (lane == 0) emit_ray(a, i, j, code);
+    }
+}
+
 // ------------------------------- batch -------------------------------------
 
 __device__ inline RecheckArgs batch_recheck_args(const BatchMap &m) {
@@ -398,12 +436,21 @@ hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_onl
     } else if (unit) {
         hipLaunchKernelGGL(recheck_fast_kernel<true>, grid, block, 0, stream, a);
         hipLaunchKernelGGL(recheck_fast_wave_kernel<true>, grid, block, 0, stream, a);
+        if (a.defer) hipLaunchKernelGGL(recheck_defer_kernel, grid, block, 0, stream, a);
         hipLaunchKernelGGL(recheck_exact_wave_kernel<true>, grid, block, 0, stream, a);
     } else {
         hipLaunchKernelGGL(recheck_fast_kernel<false>, grid, block, 0, stream, a);
         hipLaunchKernelGGL(recheck_fast_wave_kernel<false>, grid, block, 0, stream, a);
+        if (a.defer) hipLaunchKernelGGL(recheck_defer_kernel, grid, block, 0, stream, a);
         hipLaunchKernelGGL(recheck_exact_wave_kernel<false>, grid, block, 0, stream, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck_deferred(const RecheckArgs &a, hipStream_t stream) {
+    const dim3 grid(1024), block(256);
+    if (a.lens_m == nullptr) hipLaunchKernelGGL(recheck_exact_deferred_kernel<true>, grid, block, 0, stream, a);
+    else hipLaunchKernelGGL(recheck_exact_deferred_kernel<false>, grid, block, 0, stream, a);
     return hipGetLastError();
 }
 

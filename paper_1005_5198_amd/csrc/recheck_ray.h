@@ -117,52 +117,75 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 template <bool UNIT>
 __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j) {
-    __shared__ double terms[4][2][64];
+    __shared__ double2 terms[4][2][64];   // [wave][buffer][lens of the chunk]: (m/r2 d1, m/r2 d2)
     const int lane = __lane_id();
     const int w = (threadIdx.x >> 6) & 3;
     double x1, x2;
     ray_xy(a, i, j, x1, x2);
-    double a1 = 0.0, a2 = 0.0;
-    // This lane's lens of the next chunk is loaded one chunk ahead, so the memory
-    // latency overlaps the current chunk's division and sequential sum.
-    double LX = 0.0, LY = 0.0, LM = 1.0;
-    if (lane < a.n_lens) {
-        LX = lens_x(a, lane);
-        LY = lens_y(a, lane);
-        if (!UNIT) LM = lens_mass(a, lane);
-    }
-    for (int64_t k0 = 0; k0 < a.n_lens; k0 += 64) {
-        const int64_t k = k0 + lane;
-        const double X = LX, Y = LY, M = LM;
-        if (k + 64 < a.n_lens) {
-            LX = lens_x(a, k + 64);
-            LY = lens_y(a, k + 64);
-            if (!UNIT) LM = lens_mass(a, k + 64);
-        }
-        double t1 = 0.0, t2 = 0.0;
-        bool zero = false;
+    // Lane l's term of chunk c (lens 64 c + l; zero past the last lens, which adds
+    // nothing: the running sums start at +0 and never become -0).
+    bool zero = false;
+    auto term = [&](int64_t k, double X, double Y, double M) {
+        double2 t = make_double2(0.0, 0.0);
         if (k < a.n_lens) {
             const double d1 = x1 - X;
             const double d2 = x2 - Y;
             const double r2 = d1 * d1 + d2 * d2;
-            zero = (r2 == 0.0);
+            zero |= (r2 == 0.0);
             const double m = UNIT ? 1.0 : M;
             const double f = m / r2;
-            t1 = f * d1;
-            t2 = f * d2;
+            t.x = f * d1;
+            t.y = f * d2;
         }
-        if (__ballot(zero)) return CODE_SINGULAR;
-        terms[w][0][lane] = t1;
-        terms[w][1][lane] = t2;
-        wave_lds_fence();
-        const int cnt = (a.n_lens - k0) < 64 ? (int)(a.n_lens - k0) : 64;
-#pragma unroll 8
-        for (int l = 0; l < cnt; ++l) {
-            a1 += terms[w][0][l];
-            a2 += terms[w][1][l];
+        return t;
+    };
+    auto load = [&](int64_t k, double &X, double &Y, double &M) {
+        if (k < a.n_lens) {
+            X = lens_x(a, k);
+            Y = lens_y(a, k);
+            if (!UNIT) M = lens_mass(a, k);
         }
-        wave_lds_fence();   // every lane has read this chunk before the next one is written
+    };
+    const int64_t n_chunks = (a.n_lens + 63) / 64;
+    {
+        double X = 0.0, Y = 0.0, M = 1.0;
+        load(lane, X, Y, M);
+        terms[w][0][lane] = term(lane, X, Y, M);
     }
+    // Lenses are loaded P chunks ahead of their terms (slot s of the ring holds
+    // chunk c + 1 when chunk c is summed, c = s mod P), and a chunk's terms are
+    // formed while the previous chunk is summed, so neither the memory latency nor
+    // the division sits on the dependent chain of additions.
+    constexpr int P = 4;
+    double SX[P], SY[P], SM[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        SX[s] = 0.0;
+        SY[s] = 0.0;
+        SM[s] = 1.0;
+        load(64 * (s + 1) + lane, SX[s], SY[s], SM[s]);
+    }
+    wave_lds_fence();
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t c0 = 0; c0 < n_chunks; c0 += P) {
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            const int64_t c = c0 + s;
+            if (c >= n_chunks) break;
+            const double Xn = SX[s], Yn = SY[s], Mn = SM[s];
+            load(64 * (c + 1 + P) + lane, SX[s], SY[s], SM[s]);
+            const double2 tn = term(64 * (c + 1) + lane, Xn, Yn, Mn);
+            const double2 *T = terms[w][c & 1];
+#pragma unroll
+            for (int l = 0; l < 64; ++l) {   // in lens order
+                a1 += T[l].x;
+                a2 += T[l].y;
+            }
+            terms[w][(c + 1) & 1][lane] = tn;
+            wave_lds_fence();   // every lane has read chunk c, and chunk c + 1 is written
+        }
+    }
+    if (__ballot(zero)) return CODE_SINGULAR;
     const double y1 = ((1.0 - a.gamma) - a.sigma_c) * x1 - a1;
     const double y2 = ((1.0 + a.gamma) - a.sigma_c) * x2 - a2;
     const double u = (y1 - a.tx0) / (a.tw / (double)a.npx);
@@ -237,20 +260,46 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
     const double inv_pixh = (double)a.npy / a.th;
     double a1 = 0.0, a2 = 0.0, S = 0.0;
     int tiny = 0;
-    for (int64_t k = __lane_id(); k < a.n_lens; k += 64) {
-        const double d1 = x1 - lens_x(a, k);
-        const double d2 = x2 - lens_y(a, k);
-        const double r2 = __builtin_fma(d1, d1, d2 * d2);
-        tiny |= !(r2 > 1e-200);
-        double rc = __builtin_amdgcn_rcp(r2);
-        double e = __builtin_fma(-r2, rc, 1.0);
-        rc = __builtin_fma(rc, e, rc);
-        e = __builtin_fma(-r2, rc, 1.0);
-        rc = __builtin_fma(rc, e, rc);
-        if (!UNIT) rc = rc * lens_mass(a, k);
-        a1 = __builtin_fma(d1, rc, a1);
-        a2 = __builtin_fma(d2, rc, a2);
-        S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
+    // Lane l takes lenses l, l + 64, ...; U of them per step, whose positions were
+    // loaded during the previous step, so the memory latency is not waited for.
+    constexpr int U = 4;
+    double LX[U], LY[U], LM[U];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = k0 + 64 * u;
+            LX[u] = k < a.n_lens ? lens_x(a, k) : 0.0;
+            LY[u] = k < a.n_lens ? lens_y(a, k) : 0.0;
+            LM[u] = (UNIT || k >= a.n_lens) ? 1.0 : lens_mass(a, k);
+        }
+    };
+    load(__lane_id());
+    for (int64_t k0 = __lane_id(); k0 < a.n_lens; k0 += 64 * U) {
+        double X[U], Y[U], M[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            X[u] = LX[u];
+            Y[u] = LY[u];
+            M[u] = LM[u];
+        }
+        load(k0 + 64 * U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + 64 * u >= a.n_lens) break;
+            const double d1 = x1 - X[u];
+            const double d2 = x2 - Y[u];
+            const double r2 = __builtin_fma(d1, d1, d2 * d2);
+            tiny |= !(r2 > 1e-200);
+            double rc = __builtin_amdgcn_rcp(r2);
+            double e = __builtin_fma(-r2, rc, 1.0);
+            rc = __builtin_fma(rc, e, rc);
+            e = __builtin_fma(-r2, rc, 1.0);
+            rc = __builtin_fma(rc, e, rc);
+            if (!UNIT) rc = rc * M[u];
+            a1 = __builtin_fma(d1, rc, a1);
+            a2 = __builtin_fma(d2, rc, a2);
+            S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

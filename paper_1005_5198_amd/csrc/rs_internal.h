@@ -91,6 +91,8 @@ struct RecheckArgs {
     uint32_t *qunres;      // entries stage A left to the exact stage (counted by stage A), or nullptr
     int32_t random;        // Philox-random ray positions (RS_RANDOM_RAYS)
     uint64_t seed;
+    int64_t *defer;        // (i, j) pairs gathered for the exact stage after the last launch, or nullptr
+    uint32_t *dcount;      // their count (may exceed DEFER_CAP: the rest stayed with their launch)
 };
 
 // Shoot arguments of a whole window (no chunking): the same values the host
@@ -256,6 +258,8 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream);
 // Random rays: count into bins, scan, scatter, then deflect bin by bin.
 hipError_t launch_shoot_random(const ShootArgs &a, int mode, hipStream_t stream);
 hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_only, hipStream_t stream);
+// The exact stage of the rays a map's launches gathered in a.defer.
+hipError_t launch_recheck_deferred(const RecheckArgs &a, hipStream_t stream);
 // Mixed mode on the regular grid: the super-patch expansions of the launch, then
 // the far-field re-check stage over the queue (a.queue, a.qcount); it counts the
 // entries it leaves undecided in *qlive.

@@ -165,7 +165,7 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
 
     const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
     hipError_t e =
-        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 3 * pl.n_chunks, stream);
+        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 3 * pl.n_chunks + 1, stream);
     if (e != hipSuccess) return hip_fail(e, "fill kernel");
 
     char *ws = static_cast<char *>(workspace);
@@ -222,6 +222,10 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
     r.queue = a.queue;
     r.random = pl.random ? 1 : 0;
     r.seed = p->seed;
+    if (pl.defer) {
+        r.defer = reinterpret_cast<int64_t *>(ws + pl.defer_off);
+        r.dcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 3 * pl.n_chunks;
+    }
     if (pl.random) {
         a.random = 1;
         a.seed = p->seed;
@@ -316,6 +320,10 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
             e = launch_recheck(r, (a.jc1 - a.jc0) * pl.W, (p->flags & RS_EXACT_RECHECK) != 0, stream);
             if (e != hipSuccess) return hip_fail(e, "re-check kernel");
         }
+    }
+    if (pl.defer) {
+        e = launch_recheck_deferred(r, stream);
+        if (e != hipSuccess) return hip_fail(e, "deferred exact re-check kernel");
     }
     if (kernel_ms) {
         *kernel_ms = timed_ms;

@@ -60,7 +60,8 @@ std::string check(const rs_map_params &p, const Plan &pl) {
         if (pl.queue_cap < rows_cap * W) return "queue below a launch's rays";
         if (rows_cap * W - 1 >= (int64_t(1) << 30)) return "queue index reaches the mark bits";
     }
-    if (pl.qcount_bytes < WS_QCOUNT + 12 * (size_t)pl.n_chunks || pl.qcount_bytes % 256) return "qcount area";
+    // per launch: queue length, live and unresolved counts; then the deferred count
+    if (pl.qcount_bytes < WS_QCOUNT + 12 * (size_t)pl.n_chunks + 4 || pl.qcount_bytes % 256) return "qcount area";
     size_t end = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
     if (end > pl.bytes) return "queue beyond the workspace";
     if (pl.super_cap > 0) {
@@ -71,8 +72,31 @@ std::string check(const rs_map_params &p, const Plan &pl) {
         if (end > pl.bytes) return "lists beyond the workspace";
         // every patch row of the largest launch has its super-patch record
         const int64_t nbx = (W + PATCH_X - 1) / PATCH_X, nby = (rows_cap + PATCH_Y - 1) / PATCH_Y;
-        if (!pl.random && pl.super_cap < ((nbx + FF_SP_X - 1) / FF_SP_X) * ((nby + FF_SP_Y - 1) / FF_SP_Y))
-            return "too few records";
+        const int64_t sbx = (nbx + FF_SP_X - 1) / FF_SP_X, sby = (nby + FF_SP_Y - 1) / FF_SP_Y;
+        if (!pl.random && pl.super_cap < sbx * sby) return "too few records";
+        if (p.mode == RS_FARFIELD) {
+            // patch records, the patch counter, group records and group lists, in that order
+            if (pl.patch_cap < nbx * nby) return "too few patch records";
+            if (pl.ff_patch_off % 256 || pl.ff_patch_off < end) return "patch record offset";
+            end = pl.ff_patch_off + sizeof(double) * FF_PATCH_DOUBLES * (size_t)pl.patch_cap;
+            if (pl.ff_work_off % 256 || pl.ff_work_off < end) return "patch counter offset";
+            end = pl.ff_work_off + 4;
+            const int64_t groups = ((sbx + FF_GROUP - 1) / FF_GROUP) * ((sby + FF_GROUP - 1) / FF_GROUP);
+            if (pl.group_cap < groups) return "too few group records";
+            if (pl.ff_group_off % 256 || pl.ff_group_off < end) return "group record offset";
+            end = pl.ff_group_off + sizeof(double) * FF_REC_DOUBLES * (size_t)pl.group_cap;
+            if (pl.ff_glist_off % 256 || pl.ff_glist_off < end) return "group list offset";
+            end = pl.ff_glist_off + sizeof(int32_t) * (1 + (size_t)FF_GROUP_CAP) * (size_t)pl.group_cap;
+            if (end > pl.bytes) return "group lists beyond the workspace";
+        }
+    }
+    // several launches of a mode with re-checks gather their exact-stage rays
+    const bool want_defer = p.mode != RS_FP32 && !(p.flags & RS_EXACT_RECHECK) && pl.n_chunks > 1;
+    if (pl.defer != want_defer) return "deferred list";
+    if (pl.defer) {
+        if (pl.defer_off % 256 || pl.defer_off < end) return "deferred list offset";
+        end = pl.defer_off + sizeof(int64_t) * 2 * (size_t)DEFER_CAP;
+        if (end > pl.bytes) return "deferred list beyond the workspace";
     }
     if (pl.random && pl.n_chunks > 0) {
         if (pl.rays_cap < rows_cap * W) return "sorted-ray list below a launch";
