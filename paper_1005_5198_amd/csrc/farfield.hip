@@ -95,6 +95,7 @@ struct FarAcc {
         }
     }
     // Block sum into out[FAR_REC] (shared); lanes by butterfly, then waves in index order.
+    template <int THREADS = FAR_THREADS>
     __device__ void reduce(double (*part)[FAR_REC], double *out) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         butterfly();
@@ -112,18 +113,23 @@ struct FarAcc {
         __syncthreads();
         if (threadIdx.x < FAR_REC) {
             double v = 0.0;
-            for (int w = 0; w < FAR_THREADS / 64; ++w) v += part[w][threadIdx.x];
+            for (int w = 0; w < THREADS / 64; ++w) v += part[w][threadIdx.x];
             out[threadIdx.x] = v;
         }
         __syncthreads();
     }
 };
 
-struct FarSuperSmem {
-    double part[FAR_THREADS / 64][FAR_REC];
+// Shared memory of a level builder with THREADS threads.
+template <int THREADS = FAR_THREADS>
+struct FarLevelSmem {
+    double part[THREADS / 64][FAR_REC];
     double out[FAR_REC];
     int count;
 };
+using FarSuperSmem = FarLevelSmem<FAR_THREADS>;
+// Groups hold 2^19 rays and there are few of them: two blocks' worth of threads each.
+constexpr int FAR_GROUP_THREADS = 2 * FAR_THREADS;
 
 // Record of one level about (cx, cy) with half-diagonal H: of the candidates
 // (cand(q, k, X, Y) gives candidate q's lens, or false when q is none), those
@@ -135,17 +141,17 @@ struct FarSuperSmem {
 //   E_m = sum_{n>=m} binom(n, m) e^(n-m) C_n, e = z_parent - z,
 // and added, and its bound sums are added to this level's. The sums stay valid
 // bounds below: their rounding constants allow for several translations.
-template <bool UNIT, class Cand>
+template <bool UNIT, int THREADS = FAR_THREADS, class Cand>
 __device__ __forceinline__ void build_level(const ShootArgs &a, double cx, double cy, double H, int64_t n_cand, Cand cand,
                                    int32_t *list, int cap, double *rec, const double *parent, double pcx, double pcy,
-                                   FarSuperSmem &sm) {
+                                   FarLevelSmem<THREADS> &sm) {
     const double near_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
     if (threadIdx.x == 0) sm.count = 0;
     __syncthreads();
     FarAcc acc;
     acc.zero();
 #pragma unroll 1
-    for (int64_t q = threadIdx.x; q < n_cand; q += FAR_THREADS) {
+    for (int64_t q = threadIdx.x; q < n_cand; q += THREADS) {
         int64_t k;
         double X, Y;
         if (!cand(q, k, X, Y)) continue;
@@ -159,7 +165,7 @@ __device__ __forceinline__ void build_level(const ShootArgs &a, double cx, doubl
         const double m = (UNIT || a.lens_m == nullptr) ? 1.0 : ((global_double *)a.lens_m)[k];
         acc.add(d1, d2, r2, m, H);
     }
-    acc.reduce(sm.part, sm.out);
+    acc.template reduce<THREADS>(sm.part, sm.out);
     const int t = threadIdx.x;
     if (parent == nullptr) {
         if (t < FAR_REC) rec[t] = sm.out[t];
@@ -272,13 +278,14 @@ __device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, i
 
 // Far-field mode, level 0: one block per group, every lens.
 template <bool UNIT>
-__global__ __launch_bounds__(FAR_THREADS) void farfield_group_kernel(const ShootArgs a) {
-    __shared__ FarSuperSmem sm;
+__global__ __launch_bounds__(FAR_GROUP_THREADS) void farfield_group_kernel(const ShootArgs a) {
+    __shared__ FarLevelSmem<FAR_GROUP_THREADS> sm;
     const int64_t g = blockIdx.x;
     double cx, cy, H;
     group_geometry(a, g, cx, cy, H);
-    build_level<UNIT>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy}, a.ff_glist + g * (int64_t)(1 + FF_GROUP_CAP),
-                      FF_GROUP_CAP, a.ff_group + g * (int64_t)FAR_REC, nullptr, 0.0, 0.0, sm);
+    build_level<UNIT, FAR_GROUP_THREADS>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy},
+                                         a.ff_glist + g * (int64_t)(1 + FF_GROUP_CAP), FF_GROUP_CAP,
+                                         a.ff_group + g * (int64_t)FAR_REC, nullptr, 0.0, 0.0, sm);
 }
 
 // Far-field mode, level 1: one block per super-patch, candidates from its group,
@@ -715,8 +722,9 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     const bool pix = a.pix_out != nullptr;
     const dim3 block(FAR_THREADS);
     const int64_t n_group = a.ff_gbx * ((((nby + FF_SP_Y - 1) / FF_SP_Y) + FF_GROUP - 1) / FF_GROUP);
-    if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), dim3((unsigned)n_group), block, 0, stream, a);
-    else hipLaunchKernelGGL((farfield_group_kernel<false>), dim3((unsigned)n_group), block, 0, stream, a);
+    const dim3 group_block(FAR_GROUP_THREADS);
+    if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), dim3((unsigned)n_group), group_block, 0, stream, a);
+    else hipLaunchKernelGGL((farfield_group_kernel<false>), dim3((unsigned)n_group), group_block, 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (unit) hipLaunchKernelGGL((farfield_super_group_kernel<true>), dim3((unsigned)n_super), block, 0, stream, a);

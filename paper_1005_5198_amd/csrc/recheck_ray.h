@@ -122,67 +122,74 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
     const int w = (threadIdx.x >> 6) & 3;
     double x1, x2;
     ray_xy(a, i, j, x1, x2);
-    // Lane l's term of chunk c (lens 64 c + l; zero past the last lens, which adds
-    // nothing: the running sums start at +0 and never become -0).
+    double a1 = 0.0, a2 = 0.0;
     bool zero = false;
-    auto term = [&](int64_t k, double X, double Y, double M) {
-        double2 t = make_double2(0.0, 0.0);
-        if (k < a.n_lens) {
+    if (a.n_lens > 0) {
+        // Loads and terms have no branches (indices past the last lens read the last
+        // lens, and their terms are replaced by zero, which adds nothing: the running
+        // sums start at +0 and never become -0), so the compiler can count the loads
+        // in flight and wait for the oldest only.
+        const int64_t last = a.n_lens - 1;
+        auto load = [&](int64_t k, double &X, double &Y, double &M) {
+            const int64_t kc = k < a.n_lens ? k : last;
+            X = lens_x(a, kc);
+            Y = lens_y(a, kc);
+            M = UNIT ? 1.0 : lens_mass(a, kc);
+        };
+        auto term = [&](int64_t k, double X, double Y, double M) {
             const double d1 = x1 - X;
             const double d2 = x2 - Y;
             const double r2 = d1 * d1 + d2 * d2;
-            zero |= (r2 == 0.0);
+            const bool real = k < a.n_lens;
+            zero |= real && (r2 == 0.0);
             const double m = UNIT ? 1.0 : M;
             const double f = m / r2;
-            t.x = f * d1;
-            t.y = f * d2;
+            return make_double2(real ? f * d1 : 0.0, real ? f * d2 : 0.0);
+        };
+        const int64_t n_chunks = (a.n_lens + 63) / 64;
+        {
+            double X, Y, M;
+            load(lane, X, Y, M);
+            terms[w][0][lane] = term(lane, X, Y, M);
         }
-        return t;
-    };
-    auto load = [&](int64_t k, double &X, double &Y, double &M) {
-        if (k < a.n_lens) {
-            X = lens_x(a, k);
-            Y = lens_y(a, k);
-            if (!UNIT) M = lens_mass(a, k);
-        }
-    };
-    const int64_t n_chunks = (a.n_lens + 63) / 64;
-    {
-        double X = 0.0, Y = 0.0, M = 1.0;
-        load(lane, X, Y, M);
-        terms[w][0][lane] = term(lane, X, Y, M);
-    }
-    // Lenses are loaded P chunks ahead of their terms (slot s of the ring holds
-    // chunk c + 1 when chunk c is summed, c = s mod P), and a chunk's terms are
-    // formed while the previous chunk is summed, so neither the memory latency nor
-    // the division sits on the dependent chain of additions.
-    constexpr int P = 4;
-    double SX[P], SY[P], SM[P];
+        // Lens positions are loaded P chunks ahead of their terms (slot s of the ring
+        // holds chunk c + 1 while chunk c is summed, c = s mod P), and a chunk's terms
+        // are formed while the previous chunk is summed, so neither the memory latency
+        // nor the division sits on the dependent chain of additions.
+        constexpr int P = 4;
+        double SX[P], SY[P], SM[P];
 #pragma unroll
-    for (int s = 0; s < P; ++s) {
-        SX[s] = 0.0;
-        SY[s] = 0.0;
-        SM[s] = 1.0;
-        load(64 * (s + 1) + lane, SX[s], SY[s], SM[s]);
-    }
-    wave_lds_fence();
-    double a1 = 0.0, a2 = 0.0;
-    for (int64_t c0 = 0; c0 < n_chunks; c0 += P) {
+        for (int s = 0; s < P; ++s) load(64 * (s + 1) + lane, SX[s], SY[s], SM[s]);
+        wave_lds_fence();
+        // Whole rounds of P chunks: the chunks past the last one hold zero terms.
+        for (int64_t c0 = 0; c0 < n_chunks; c0 += P) {
 #pragma unroll
-        for (int s = 0; s < P; ++s) {
-            const int64_t c = c0 + s;
-            if (c >= n_chunks) break;
-            const double Xn = SX[s], Yn = SY[s], Mn = SM[s];
-            load(64 * (c + 1 + P) + lane, SX[s], SY[s], SM[s]);
-            const double2 tn = term(64 * (c + 1) + lane, Xn, Yn, Mn);
-            const double2 *T = terms[w][c & 1];
+            for (int s = 0; s < P; ++s) {
+                const int64_t c = c0 + s;
+                const double2 tn = term(64 * (c + 1) + lane, SX[s], SY[s], SM[s]);
+                load(64 * (c + 1 + P) + lane, SX[s], SY[s], SM[s]);
+                const double2 *T = terms[w][c & 1];
+                // in lens order, eight terms read ahead of their additions
+                constexpr int B = 8;
+                double2 cur[B];
 #pragma unroll
-            for (int l = 0; l < 64; ++l) {   // in lens order
-                a1 += T[l].x;
-                a2 += T[l].y;
+                for (int l = 0; l < B; ++l) cur[l] = T[l];
+#pragma unroll
+                for (int g = 0; g < 64 / B; ++g) {
+                    double2 nxt[B];
+#pragma unroll
+                    for (int l = 0; l < B; ++l) nxt[l] = T[(B * (g + 1) + l) & 63];
+#pragma unroll
+                    for (int l = 0; l < B; ++l) {
+                        a1 += cur[l].x;
+                        a2 += cur[l].y;
+                    }
+#pragma unroll
+                    for (int l = 0; l < B; ++l) cur[l] = nxt[l];
+                }
+                terms[w][(c + 1) & 1][lane] = tn;
+                wave_lds_fence();   // every lane has read chunk c, and chunk c + 1 is written
             }
-            terms[w][(c + 1) & 1][lane] = tn;
-            wave_lds_fence();   // every lane has read chunk c, and chunk c + 1 is written
         }
     }
     if (__ballot(zero)) return CODE_SINGULAR;
@@ -262,18 +269,21 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
     int tiny = 0;
     // Lane l takes lenses l, l + 64, ...; U of them per step, whose positions were
     // loaded during the previous step, so the memory latency is not waited for.
+    // Loads past the last lens read the last lens and their terms are dropped, so
+    // the loop has no branches and the compiler can count the loads in flight.
     constexpr int U = 4;
     double LX[U], LY[U], LM[U];
+    const int64_t last = a.n_lens - 1;
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t k = k0 + 64 * u;
-            LX[u] = k < a.n_lens ? lens_x(a, k) : 0.0;
-            LY[u] = k < a.n_lens ? lens_y(a, k) : 0.0;
-            LM[u] = (UNIT || k >= a.n_lens) ? 1.0 : lens_mass(a, k);
+            const int64_t k = k0 + 64 * u < a.n_lens ? k0 + 64 * u : last;
+            LX[u] = lens_x(a, k);
+            LY[u] = lens_y(a, k);
+            LM[u] = UNIT ? 1.0 : lens_mass(a, k);
         }
     };
-    load(__lane_id());
+    if (a.n_lens > 0) load(__lane_id());
     for (int64_t k0 = __lane_id(); k0 < a.n_lens; k0 += 64 * U) {
         double X[U], Y[U], M[U];
 #pragma unroll
@@ -285,17 +295,18 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
         load(k0 + 64 * U);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (k0 + 64 * u >= a.n_lens) break;
+            const bool real = k0 + 64 * u < a.n_lens;
             const double d1 = x1 - X[u];
             const double d2 = x2 - Y[u];
             const double r2 = __builtin_fma(d1, d1, d2 * d2);
-            tiny |= !(r2 > 1e-200);
+            tiny |= real && !(r2 > 1e-200);
             double rc = __builtin_amdgcn_rcp(r2);
             double e = __builtin_fma(-r2, rc, 1.0);
             rc = __builtin_fma(rc, e, rc);
             e = __builtin_fma(-r2, rc, 1.0);
             rc = __builtin_fma(rc, e, rc);
             if (!UNIT) rc = rc * M[u];
+            rc = real ? rc : 0.0;
             a1 = __builtin_fma(d1, rc, a1);
             a2 = __builtin_fma(d2, rc, a2);
             S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
