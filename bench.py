@@ -27,6 +27,7 @@ import argparse
 import json
 import os
 import sys
+import hashlib
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -37,9 +38,25 @@ FLOP_PER_INTERACTION = 10      # the paper's N_FLOP (Section 2, Phi); one deflec
 METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batched vs plain"
 
 # HBM bytes per launch of the mixed-mode deflection kernel on this workload: rocprofv3 --pmc
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB copy), measured on the current
-# kernel (profiles/shoot_kernel_config2.md). Set to None whenever the kernel changes.
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB copy), from the counters in
+# profiles/shoot_kernel_config2.md, taken with the kernel sources whose digest follows. When any
+# of those sources differs, the figure no longer describes the kernel and is reported as null.
 TRAFFIC_BYTES_PER_LAUNCH = 1.476e9
+TRAFFIC_SOURCES = ("shoot.hip", "shoot_common.h", "recheck_ray.h", "rs_internal.h", "rs_layout.h")
+TRAFFIC_SOURCES_DIGEST = None
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1005_5198_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """The counters' bytes per launch when they were taken on the sources built here, else None."""
+    return TRAFFIC_BYTES_PER_LAUNCH if kernel_sources_digest() == TRAFFIC_SOURCES_DIGEST else None
 
 
 def parse():
@@ -193,7 +210,7 @@ def main():
         "non_deflection_share": (ms_per_step - kernel_ms / args.steps) / ms_per_step,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_PEAK_TFLOPS,
-                     "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                     "traffic": measured_traffic(), "traffic_sources_digest": kernel_sources_digest(),
                      "kernel": "shoot_kernel (deflection + binning)",
                      "launches": launches, "mean_launch_ms": kernel_ms / max(launches, 1)},
         "thread_shape": None if tuned is None else tuned["shapes"][tuned["best"]]["rays_per_lane"],
