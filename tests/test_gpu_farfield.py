@@ -85,6 +85,21 @@ def test_farfield_crowded_and_singular(rs):
     check_exact(rs, sub)
 
 
+def test_farfield_list_overflows(rs):
+    """20000 lenses of masses +1 and -1 in a disc of radius 40 over the config-0 grid: more than
+    16384 lenses near a group (its list overflows: its super-patches scan every lens), more than
+    4096 near a super-patch (the patches scan every lens with both tests), and 25 to 512 within
+    four half-diagonals of a patch (more than its record holds: the ray kernel finds them
+    itself)."""
+    rng = np.random.default_rng(25)
+    s = w.config0()
+    lenses = w.lenses_in_disc(20000, 40.0, rng)
+    masses = np.where(np.arange(20000) % 2 == 0, 1.0, -1.0)
+    sub = w.MapSpec("overflows", s.params, lenses, masses).window(448, 576, 480, 544)
+    st = check_exact(rs, sub)
+    say(f"  re-checked {st['rays_rechecked']}")
+
+
 def test_farfield_config2_full_equals_mixed(rs):
     """The full 19200 x 3840-ray map: the far-field map equals the mixed-mode map (itself the
     oracle's, see the parity tests), and sampled rays equal the oracle's one by one."""

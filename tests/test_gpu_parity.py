@@ -331,6 +331,28 @@ def test_far_field_recheck_list_overflow(rs):
     assert st["rays_rechecked_direct"] == st["rays_rechecked"]
 
 
+@pytest.mark.parametrize("mode", ["mixed", "farfield"])
+def test_exact_stage_gathered_over_launches_and_its_overflow(rs, mode):
+    """A map of two launches (8192 x 16400 rays) whose every 33rd column lands exactly on a pixel
+    edge (one massless lens: no deflection, y = x; pixels 33/64 wide, rays 1/64 apart): no bound
+    can place those 4.1e6 rays, so they all reach the exact stage. The first 65536 are gathered
+    over both launches and run after the last one, the rest with their own launch; the map and
+    the counts equal the oracle's."""
+    nx, ny = 8192, 16400                       # 2^27 + 16 x 8192 rays: two launches
+    shoot = (-64.0 - 0.5 / 64, -128.0, 128.0, ny / 64.0, nx, ny)   # x = i/64 - 64, y = (j + 1/2)/64 - 128
+    src = (-64.0, -128.0, 132.0, 256.25, 256, 8200)                 # 33/64 x 1/32 pixels
+    p = w.make_params(0.0, 0.0, 0.0, shoot, src)
+    spec = w.MapSpec("edges", p, np.array([[1000.0, 1000.0]]), np.array([0.0]))
+    m_o, st_o = oracle.make_map(spec.params, spec.lens_xy, spec.lens_m)
+    m_g, st_g = gpu_map(rs, spec, mode)
+    on_edge = len(range(0, nx, 33)) * ny
+    say(f"{mode}: re-checked {st_g['rays_rechecked']}, rays on an edge {on_edge}")
+    assert st_g["rays_rechecked"] >= on_edge > 65536
+    assert np.array_equal(m_g, m_o), f"map differs in {int(np.count_nonzero(m_g != m_o))} pixels"
+    assert st_g["rays_in_map"] == st_o["rays_in_map"] == nx * ny
+    assert st_g["rays_out"] == st_o["rays_out"] == 0
+
+
 def test_batch_far_field_stage_list_overflow(rs):
     """A batch whose first map's super-patch lists overflow (5000 lenses within reach of every
     super-patch) next to an ordinary map: the overflowing map's flagged rays all take the stage
