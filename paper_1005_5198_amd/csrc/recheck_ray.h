@@ -202,39 +202,21 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
     return CODE_OUT;
 }
 
-// Stage A. Returns true (and the definition's code) when the ray is decided.
-template <bool UNIT>
-__device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
+// Stage A's pixel decision. (a1, a2) is this stage's FP64 sum, S = sum (|d1| + |d2|) |m| / r^2
+// over every lens, and t1, t2 bound |definition's a_i - this a_i| (both roundings added); the
+// ray is decided when its position is farther than that, plus both epilogues' rounding, from
+// every pixel edge.
+__device__ inline bool stage_a_decide(const RecheckArgs &a, double x1, double x2, double a1, double a2, double S,
+                                      double t1, double t2, bool tiny, int &code) {
     const double U64 = 1.1102230246251565e-16;  // 2^-53
-    double x1, x2;
-    ray_xy(a, i, j, x1, x2);
     const double c1 = (1.0 - a.gamma) - a.sigma_c;
     const double c2 = (1.0 + a.gamma) - a.sigma_c;
     const double inv_pixw = (double)a.npx / a.tw;
     const double inv_pixh = (double)a.npy / a.th;
-    double a1 = 0.0, a2 = 0.0, S = 0.0;
-    bool tiny = false;
-#pragma unroll 4
-    for (int64_t k = 0; k < a.n_lens; ++k) {
-        const double d1 = x1 - lens_x(a, k);
-        const double d2 = x2 - lens_y(a, k);
-        const double r2 = __builtin_fma(d1, d1, d2 * d2);
-        tiny |= !(r2 > 1e-200);
-        double rc = __builtin_amdgcn_rcp(r2);
-        double e = __builtin_fma(-r2, rc, 1.0);
-        rc = __builtin_fma(rc, e, rc);
-        e = __builtin_fma(-r2, rc, 1.0);
-        rc = __builtin_fma(rc, e, rc);
-        if (!UNIT) rc = rc * lens_mass(a, k);
-        a1 = __builtin_fma(d1, rc, a1);
-        a2 = __builtin_fma(d2, rc, a2);
-        S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
-    }
-    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
     const double u = (c1 * x1 - a1 - a.tx0) * inv_pixw;
     const double v = (c2 * x2 - a2 - a.ty0) * inv_pixh;
-    const double Mu = 2.002 * (kN * S + 8.0 * U64 * (fabs(c1 * x1) + fabs(a1) + fabs(a.tx0))) * inv_pixw;
-    const double Mv = 2.002 * (kN * S + 8.0 * U64 * (fabs(c2 * x2) + fabs(a2) + fabs(a.ty0))) * inv_pixh;
+    const double Mu = (t1 + 2.002 * 8.0 * U64 * (fabs(c1 * x1) + fabs(a1) + fabs(a.tx0))) * inv_pixw;
+    const double Mv = (t2 + 2.002 * 8.0 * U64 * (fabs(c2 * x2) + fabs(a2) + fabs(a.ty0))) * inv_pixh;
     const double fu = floor(u), fv = floor(v);
     const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
     const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
@@ -252,26 +234,86 @@ __device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int 
     return false;
 }
 
-// Stage A by a whole wave for one ray (i, j wave-uniform): lanes take every 64th
-// lens, then the partial sums meet in a fixed butterfly. Any summation order
-// stays within the same bound, (N + 10) 2^-53 S, so the decision rule is
-// fast_ray's. Every lane returns the same result.
-template <bool UNIT>
-__device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
+// The bound t of stage_a_decide. Any summation order of N terms stays within (N + 10) 2^-53 S
+// of the exact sum, so 2 (N + 10) 2^-53 S covers both evaluations (any_order). Tighter, from the
+// partial sums: the definition adds its terms in lens order and the k-th addition's rounding is
+// at most 2^-53 |s_k| (s_k its partial sum), so its sum is within 2^-53 sum_k |s_k| of its own
+// terms' exact sum, and that within 8 2^-53 S of the exact one (per-term rounding). This stage
+// estimates sum_k |s_k|; the two functions below add its error and this stage's own. Constants
+// are rounded up; N 2^-53 < 1e-3 for every map the library takes.
+__device__ inline double any_order_bound(int64_t n_lens, double S) {
     const double U64 = 1.1102230246251565e-16;  // 2^-53
+    return 2.002 * ((double)n_lens + 10.0) * U64 * 1.001 * S;
+}
+
+// This stage summing in lens order itself (one thread per ray): Q = sum_k |running sum after
+// lens k|. Its own sum is within 8 2^-53 S + 2^-53 Q, its partial sums within that of the
+// definition's terms' partial sums, so sum_k |s_k| <= Q (1 + N 2^-53) + 16 N 2^-53 S.
+__device__ inline double sequential_bound(int64_t n_lens, double S, double Q) {
+    const double U64 = 1.1102230246251565e-16;  // 2^-53
+    const double N = (double)n_lens;
+    const double partial = 1.001 * (16.0 * U64 * S + 2.2 * U64 * Q + 17.0 * N * U64 * U64 * S);
+    return fmin(any_order_bound(n_lens, S), partial);
+}
+
+// This stage summing lenses in blocks of B in lens order (one wave per ray, the lanes' sums
+// combined at every block's end): Q = sum over block starts of |partial sum|. For lens k of a
+// block, |s_k| <= |s at the block's start| + the block's sum of |terms|, so sum_k |s_k| <=
+// B Q + B S plus each block start's error (its sum depth e: e 2^-53 S, plus 16 2^-53 S for the
+// two term evaluations); this stage's own sum is within (e + 8) 2^-53 S.
+__device__ inline double block_bound(int64_t n_lens, double S, double Q, double B, double e) {
+    const double U64 = 1.1102230246251565e-16;  // 2^-53
+    const double N = (double)n_lens;
+    const double partial = 1.001 * ((e + 32.0 + 1.05 * B) * U64 * S + 1.05 * B * U64 * Q +
+                                    1.05 * (N + B) * (e + 32.0) * U64 * U64 * S);
+    return fmin(any_order_bound(n_lens, S), partial);
+}
+
+// Stage A. Returns true (and the definition's code) when the ray is decided.
+template <bool UNIT>
+__device__ inline bool fast_ray(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
     double x1, x2;
     ray_xy(a, i, j, x1, x2);
-    const double c1 = (1.0 - a.gamma) - a.sigma_c;
-    const double c2 = (1.0 + a.gamma) - a.sigma_c;
-    const double inv_pixw = (double)a.npx / a.tw;
-    const double inv_pixh = (double)a.npy / a.th;
-    double a1 = 0.0, a2 = 0.0, S = 0.0;
+    double a1 = 0.0, a2 = 0.0, S = 0.0, Q1 = 0.0, Q2 = 0.0;
+    bool tiny = false;
+#pragma unroll 4
+    for (int64_t k = 0; k < a.n_lens; ++k) {
+        const double d1 = x1 - lens_x(a, k);
+        const double d2 = x2 - lens_y(a, k);
+        const double r2 = __builtin_fma(d1, d1, d2 * d2);
+        tiny |= !(r2 > 1e-200);
+        double rc = __builtin_amdgcn_rcp(r2);
+        double e = __builtin_fma(-r2, rc, 1.0);
+        rc = __builtin_fma(rc, e, rc);
+        e = __builtin_fma(-r2, rc, 1.0);
+        rc = __builtin_fma(rc, e, rc);
+        if (!UNIT) rc = rc * lens_mass(a, k);
+        a1 = __builtin_fma(d1, rc, a1);
+        a2 = __builtin_fma(d2, rc, a2);
+        S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
+        Q1 += fabs(a1);
+        Q2 += fabs(a2);
+    }
+    return stage_a_decide(a, x1, x2, a1, a2, S, sequential_bound(a.n_lens, S, Q1),
+                          sequential_bound(a.n_lens, S, Q2), tiny, code);
+}
+
+// Stage A by a whole wave for one ray (i, j wave-uniform): lanes take every 64th lens, U of
+// them per step; every L steps (blocks of B = 64 U L lenses in lens order) the lanes' running
+// sums are added over the wave to give the partial sum at the block's end, whose magnitudes
+// feed block_bound; the totals meet in the same butterfly. Every lane returns the same result.
+template <bool UNIT>
+__device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j, int &code) {
+    double x1, x2;
+    ray_xy(a, i, j, x1, x2);
+    double a1 = 0.0, a2 = 0.0, S = 0.0, Q1 = 0.0, Q2 = 0.0;
     int tiny = 0;
     // Lane l takes lenses l, l + 64, ...; U of them per step, whose positions were
     // loaded during the previous step, so the memory latency is not waited for.
     // Loads past the last lens read the last lens and their terms are dropped, so
     // the loop has no branches and the compiler can count the loads in flight.
-    constexpr int U = 4;
+    constexpr int U = 4, L = 4;
+    constexpr double B = 64.0 * U * L;
     double LX[U], LY[U], LM[U];
     const int64_t last = a.n_lens - 1;
     auto load = [&](int64_t k0) {
@@ -283,8 +325,15 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
             LM[u] = UNIT ? 1.0 : lens_mass(a, k);
         }
     };
+    auto wave_sum = [](double v) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        return v;
+    };
+    const int64_t steps = (a.n_lens + 64 * U - 1) / (64 * U);   // the same for every lane
     if (a.n_lens > 0) load(__lane_id());
-    for (int64_t k0 = __lane_id(); k0 < a.n_lens; k0 += 64 * U) {
+    for (int64_t it = 0; it < steps; ++it) {
+        const int64_t k0 = __lane_id() + 64 * U * it;
         double X[U], Y[U], M[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -311,34 +360,20 @@ __device__ inline bool fast_ray_wave(const RecheckArgs &a, int64_t i, int64_t j,
             a2 = __builtin_fma(d2, rc, a2);
             S = __builtin_fma(fabs(d1) + fabs(d2), fabs(rc), S);
         }
+        if (it % L == L - 1 || it == steps - 1) {   // a block's end: its partial sums
+            Q1 += fabs(wave_sum(a1));
+            Q2 += fabs(wave_sum(a2));
+        }
     }
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    S = wave_sum(S);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a1 += __shfl_xor(a1, off);
-        a2 += __shfl_xor(a2, off);
-        S += __shfl_xor(S, off);
-        tiny |= __shfl_xor(tiny, off);
-    }
-    const double kN = ((double)a.n_lens + 10.0) * U64 * 1.001;
-    const double u = (c1 * x1 - a1 - a.tx0) * inv_pixw;
-    const double v = (c2 * x2 - a2 - a.ty0) * inv_pixh;
-    const double Mu = 2.002 * (kN * S + 8.0 * U64 * (fabs(c1 * x1) + fabs(a1) + fabs(a.tx0))) * inv_pixw;
-    const double Mv = 2.002 * (kN * S + 8.0 * U64 * (fabs(c2 * x2) + fabs(a2) + fabs(a.ty0))) * inv_pixh;
-    const double fu = floor(u), fv = floor(v);
-    const bool ok_u = (fmin(u - fu, fu + 1.0 - u) > Mu) && (fu >= 0.0) && (fu < (double)a.npx);
-    const bool ok_v = (fmin(v - fv, fv + 1.0 - v) > Mv) && (fv >= 0.0) && (fv < (double)a.npy);
-    const bool out_u = (u < -Mu) || (u > (double)a.npx + Mu);
-    const bool out_v = (v < -Mv) || (v > (double)a.npy + Mv);
-    const bool sane = !tiny && isfinite(S) && isfinite(Mu) && isfinite(Mv);
-    if (sane && ok_u && ok_v) {
-        code = (int)((int64_t)fv * a.npx + (int64_t)fu);
-        return true;
-    }
-    if (sane && (out_u || out_v)) {
-        code = CODE_OUT;
-        return true;
-    }
-    return false;
+    for (int off = 32; off > 0; off >>= 1) tiny |= __shfl_xor(tiny, off);
+    // a partial sum's depth: a lane's running sum plus the six butterfly levels
+    const double depth = (double)steps * U + 6.0;
+    return stage_a_decide(a, x1, x2, a1, a2, S, block_bound(a.n_lens, S, Q1, B, depth),
+                          block_bound(a.n_lens, S, Q2, B, depth), tiny != 0, code);
 }
 
 // Bin one re-checked ray (or write its pixel) and count it in the map's counters.
