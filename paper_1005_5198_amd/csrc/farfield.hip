@@ -137,14 +137,15 @@ constexpr int FAR_GROUP_THREADS = 2 * FAR_THREADS;
 // bound sums; the others go to list (count in list[0]; a count above cap means
 // the list is incomplete and the level below scans every lens instead). With a
 // parent record about (pcx, pcy) (a level above, whose own candidates these
-// are), the parent's expansion is re-centred exactly on (cx, cy),
+// are; held as n_parts records to be added in order), the parent's expansion is
+// re-centred exactly on (cx, cy),
 //   E_m = sum_{n>=m} binom(n, m) e^(n-m) C_n, e = z_parent - z,
 // and added, and its bound sums are added to this level's. The sums stay valid
 // bounds below: their rounding constants allow for several translations.
 template <bool UNIT, int THREADS = FAR_THREADS, class Cand>
 __device__ __forceinline__ void build_level(const ShootArgs &a, double cx, double cy, double H, int64_t n_cand, Cand cand,
-                                   int32_t *list, int cap, double *rec, const double *parent, double pcx, double pcy,
-                                   FarLevelSmem<THREADS> &sm) {
+                                   int32_t *list, int cap, double *rec, const double *parent, int n_parts,
+                                   double pcx, double pcy, FarLevelSmem<THREADS> &sm) {
     const double near_r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
     if (threadIdx.x == 0) sm.count = 0;
     __syncthreads();
@@ -170,14 +171,19 @@ __device__ __forceinline__ void build_level(const ShootArgs &a, double cx, doubl
     if (parent == nullptr) {
         if (t < FAR_REC) rec[t] = sm.out[t];
     } else {
-        const global_double *P = (const global_double *)parent;
+        const global_double *Pp = (const global_double *)parent;
+        auto P = [&](int n) {
+            double v = Pp[n];
+            for (int part = 1; part < n_parts; ++part) v += Pp[part * FAR_REC + n];
+            return v;
+        };
         if (t < FAR_P) {
             const double e1 = pcx - cx, e2 = pcy - cy;
             double s1 = 0.0, s2 = 0.0;
             double g1 = 1.0, g2 = 0.0;   // e^(n-m)
             for (int n = t; n < FAR_P; ++n) {
                 const double binom = BINOM[n][t];   // exact in FP64 for n < 16
-                const double C1 = P[n], C2 = P[FAR_P + n];
+                const double C1 = P(n), C2 = P(FAR_P + n);
                 s1 = __builtin_fma(binom, g1 * C1 - g2 * C2, s1);
                 s2 = __builtin_fma(binom, g1 * C2 + g2 * C1, s2);
                 const double q1 = g1 * e1 - g2 * e2, q2 = g1 * e2 + g2 * e1;
@@ -187,19 +193,20 @@ __device__ __forceinline__ void build_level(const ShootArgs &a, double cx, doubl
             rec[t] = s1 + sm.out[t];
             rec[FAR_P + t] = s2 + sm.out[FAR_P + t];
         } else if (t < FAR_P + FAR_EXTRA) {
-            rec[2 * FAR_P + (t - FAR_P)] = P[2 * FAR_P + (t - FAR_P)] + sm.out[2 * FAR_P + (t - FAR_P)];
+            rec[2 * FAR_P + (t - FAR_P)] = P(2 * FAR_P + (t - FAR_P)) + sm.out[2 * FAR_P + (t - FAR_P)];
         }
     }
     if (t == 0) list[0] = sm.count;
 }
 
-// Every lens is a candidate.
+// Every lens from index first on is a candidate.
 struct AllLenses {
     const double *xy;
+    int64_t first;
     __device__ bool operator()(int64_t q, int64_t &k, double &X, double &Y) const {
-        k = q;
-        X = ((global_double *)xy)[2 * q];
-        Y = ((global_double *)xy)[2 * q + 1];
+        k = first + q;
+        X = ((global_double *)xy)[2 * k];
+        Y = ((global_double *)xy)[2 * k + 1];
         return true;
     }
 };
@@ -211,8 +218,8 @@ template <bool UNIT>
 __device__ __forceinline__ void build_super(const ShootArgs &a, int64_t sp, FarSuperSmem &sm) {
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
-    build_level<UNIT>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy}, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
-                      a.ff_super + sp * (int64_t)FAR_REC, nullptr, 0.0, 0.0, sm);
+    build_level<UNIT>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy, 0}, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
+                      a.ff_super + sp * (int64_t)FAR_REC, nullptr, 0, 0.0, 0.0, sm);
 }
 
 // Level 1 of one launch (or, for random rays, of the whole rectangle): one block
@@ -223,6 +230,11 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_kernel(const Shoot
     __shared__ FarSuperSmem sm;
     if (RECHECK && *a.qcount == 0) return;
     build_super<UNIT>(a, blockIdx.x, sm);
+}
+
+// Blocks that scan one group's lenses: one per 8192 lenses, at most FF_GROUP_PARTS.
+__host__ __device__ inline int group_parts(int64_t n_lens) {
+    return n_lens / 8192 + 1 < FF_GROUP_PARTS ? (int)(n_lens / 8192 + 1) : FF_GROUP_PARTS;
 }
 
 // Far-field mode, level 0: groups of FF_GROUP x FF_GROUP super-patches (centre
@@ -243,21 +255,30 @@ __device__ __forceinline__ int64_t group_of(const ShootArgs &a, int64_t sp) {
     return ((sp / a.ff_sbx) / FF_GROUP) * a.ff_gbx + (sp % a.ff_sbx) / FF_GROUP;
 }
 
-// A level's candidates from the list of the level above (centre (cx, cy),
-// radius FAR_RATIO H), or, when that list overflowed, every lens that level
-// did not expand (the same test it made).
+// A super-patch's candidates: its group's lists (one per part, in part order), or,
+// when one of them overflowed, every lens the group did not expand (the same test
+// it made).
 struct ListCandidates {
+    static_assert(FF_GROUP_PARTS == 4, "three part ends below");
     const double *xy;
-    const global_i32 *list;
+    const global_i32 *lists;   // the parts' lists, 1 + FF_PART_CAP apart
+    int64_t e0, e1, e2;        // candidates before the end of parts 0, 1, 2
     bool scan_all;
     double cx, cy, r2;
     __device__ bool operator()(int64_t q, int64_t &k, double &X, double &Y) const {
-        k = scan_all ? q : (int64_t)list[1 + q];
+        if (scan_all) {
+            k = q;
+        } else {
+            const int64_t a0 = q >= e0, a1 = q >= e1, a2 = q >= e2;
+            const int64_t part = a0 + a1 + a2;
+            const int64_t before = a0 * e0 + a1 * (e1 - e0) + a2 * (e2 - e1);
+            k = (int64_t)lists[part * (1 + FF_PART_CAP) + 1 + (q - before)];
+        }
         X = ((global_double *)xy)[2 * k];
         Y = ((global_double *)xy)[2 * k + 1];
         if (scan_all) {
-            const double e1 = cx - X, e2 = cy - Y;
-            if (e1 * e1 + e2 * e2 >= r2) return false;
+            const double f1 = cx - X, f2 = cy - Y;
+            if (f1 * f1 + f2 * f2 >= r2) return false;
         }
         return true;
     }
@@ -269,23 +290,36 @@ __device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, i
     double H;
     group_geometry(a, g, c.cx, c.cy, H);
     c.r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
-    c.list = (const global_i32 *)(a.ff_glist + g * (int64_t)(1 + FF_GROUP_CAP));
-    const int32_t listed = c.list[0];
-    c.scan_all = listed > FF_GROUP_CAP;
-    n = c.scan_all ? a.n_lens : listed;
+    c.lists = (const global_i32 *)(a.ff_glist + g * FF_GROUP_PARTS * (int64_t)(1 + FF_PART_CAP));
+    const int used = group_parts(a.n_lens);   // the parts' lists past these were not written
+    const int32_t n0 = c.lists[0];
+    const int32_t n1 = used > 1 ? c.lists[1 + FF_PART_CAP] : 0;
+    const int32_t n2 = used > 2 ? c.lists[2 * (1 + FF_PART_CAP)] : 0;
+    const int32_t n3 = used > 3 ? c.lists[3 * (1 + FF_PART_CAP)] : 0;
+    c.scan_all = n0 > FF_PART_CAP || n1 > FF_PART_CAP || n2 > FF_PART_CAP || n3 > FF_PART_CAP;
+    c.e0 = n0;
+    c.e1 = c.e0 + n1;
+    c.e2 = c.e1 + n2;
+    n = c.scan_all ? a.n_lens : c.e2 + n3;
     return c;
 }
 
-// Far-field mode, level 0: one block per group, every lens.
+// Far-field mode, level 0: group_parts(N) blocks per group, each over its range of
+// lens indices.
 template <bool UNIT>
 __global__ __launch_bounds__(FAR_GROUP_THREADS) void farfield_group_kernel(const ShootArgs a) {
     __shared__ FarLevelSmem<FAR_GROUP_THREADS> sm;
-    const int64_t g = blockIdx.x;
+    const int used = group_parts(a.n_lens);
+    const int64_t g = blockIdx.x / used;
+    const int part = (int)(blockIdx.x % used);
+    const int64_t first = a.n_lens * part / used;
+    const int64_t last = a.n_lens * (part + 1) / used;
     double cx, cy, H;
     group_geometry(a, g, cx, cy, H);
-    build_level<UNIT, FAR_GROUP_THREADS>(a, cx, cy, H, a.n_lens, AllLenses{a.lens_xy},
-                                         a.ff_glist + g * (int64_t)(1 + FF_GROUP_CAP), FF_GROUP_CAP,
-                                         a.ff_group + g * (int64_t)FAR_REC, nullptr, 0.0, 0.0, sm);
+    const int64_t slot = g * FF_GROUP_PARTS + part;
+    build_level<UNIT, FAR_GROUP_THREADS>(a, cx, cy, H, last - first, AllLenses{a.lens_xy, first},
+                                         a.ff_glist + slot * (int64_t)(1 + FF_PART_CAP), FF_PART_CAP,
+                                         a.ff_group + slot * (int64_t)FAR_REC, nullptr, 0, 0.0, 0.0, sm);
 }
 
 // Far-field mode, level 1: one block per super-patch, candidates from its group,
@@ -300,7 +334,8 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_group_kernel(const
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
     build_level<UNIT>(a, cx, cy, H, n, c, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
-                      a.ff_super + sp * (int64_t)FAR_REC, a.ff_group + g * (int64_t)FAR_REC, c.cx, c.cy, sm);
+                      a.ff_super + sp * (int64_t)FAR_REC, a.ff_group + g * FF_GROUP_PARTS * (int64_t)FAR_REC,
+                      group_parts(a.n_lens), c.cx, c.cy, sm);
 }
 
 // Level 1 of every map of a mixed batch that flagged rays: one block per
@@ -723,8 +758,9 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     const dim3 block(FAR_THREADS);
     const int64_t n_group = a.ff_gbx * ((((nby + FF_SP_Y - 1) / FF_SP_Y) + FF_GROUP - 1) / FF_GROUP);
     const dim3 group_block(FAR_GROUP_THREADS);
-    if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), dim3((unsigned)n_group), group_block, 0, stream, a);
-    else hipLaunchKernelGGL((farfield_group_kernel<false>), dim3((unsigned)n_group), group_block, 0, stream, a);
+    const dim3 group_grid((unsigned)(n_group * group_parts(a.n_lens)));
+    if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), group_grid, group_block, 0, stream, a);
+    else hipLaunchKernelGGL((farfield_group_kernel<false>), group_grid, group_block, 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (unit) hipLaunchKernelGGL((farfield_super_group_kernel<true>), dim3((unsigned)n_super), block, 0, stream, a);

@@ -95,9 +95,9 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
             const int64_t sbx = (nbx + FF_SP_X - 1) / FF_SP_X, sby = (nby + FF_SP_Y - 1) / FF_SP_Y;
             pl.group_cap = ((sbx + FF_GROUP - 1) / FF_GROUP) * ((sby + FF_GROUP - 1) / FF_GROUP);
             pl.ff_group_off = off;
-            off += a256(sizeof(double) * FF_REC_DOUBLES * (size_t)pl.group_cap);
+            off += a256(sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.group_cap);
             pl.ff_glist_off = off;
-            off += a256(sizeof(int32_t) * (1 + (size_t)FF_GROUP_CAP) * (size_t)pl.group_cap);
+            off += a256(sizeof(int32_t) * (1 + (size_t)FF_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.group_cap);
         }
         pl.bytes = off;
     }

@@ -67,8 +67,8 @@ struct ShootArgs {
     double *ff_patch;      // far-field mode: [patches of the launch][FF_PATCH_DOUBLES] patch records
     uint32_t *ff_work;     // far-field mode: next patch to take (reset by the record kernel)
     int64_t ff_gbx;        // far-field mode: groups (FF_GROUP x FF_GROUP super-patches) along x
-    double *ff_group;      // far-field mode: [groups][FF_REC_DOUBLES] group records
-    int32_t *ff_glist;     // far-field mode: [groups][1 + FF_GROUP_CAP] count, then the nearer lenses
+    double *ff_group;      // far-field mode: [groups][FF_GROUP_PARTS][FF_REC_DOUBLES] group records, per part
+    int32_t *ff_glist;     // far-field mode: [groups][FF_GROUP_PARTS][1 + FF_PART_CAP] count, then the nearer lenses
 };
 
 

@@ -42,7 +42,11 @@ constexpr int FF_REC_DOUBLES = 36;
 // Far-field mode: groups of FF_GROUP x FF_GROUP super-patches above the
 // super-patches (their lists hold the candidates of their super-patches).
 constexpr int FF_GROUP = 4;
+// A group's lenses are scanned by FF_GROUP_PARTS blocks, each over a contiguous range of lens
+// indices with a record and a list (of capacity FF_GROUP_CAP / FF_GROUP_PARTS) of its own.
+constexpr int FF_GROUP_PARTS = 4;
 constexpr int FF_GROUP_CAP = 16384;
+constexpr int FF_PART_CAP = FF_GROUP_CAP / FF_GROUP_PARTS;
 // Far-field mode, per 64 x 32-ray patch: the local expansion about the patch
 // centre (16 real, 16 imaginary coefficients), the bound terms SFAR, far_err and
 // SDEF, the number of near lenses (summed directly), three spare doubles, then

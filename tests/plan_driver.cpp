@@ -84,9 +84,9 @@ std::string check(const rs_map_params &p, const Plan &pl) {
             const int64_t groups = ((sbx + FF_GROUP - 1) / FF_GROUP) * ((sby + FF_GROUP - 1) / FF_GROUP);
             if (pl.group_cap < groups) return "too few group records";
             if (pl.ff_group_off % 256 || pl.ff_group_off < end) return "group record offset";
-            end = pl.ff_group_off + sizeof(double) * FF_REC_DOUBLES * (size_t)pl.group_cap;
+            end = pl.ff_group_off + sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.group_cap;
             if (pl.ff_glist_off % 256 || pl.ff_glist_off < end) return "group list offset";
-            end = pl.ff_glist_off + sizeof(int32_t) * (1 + (size_t)FF_GROUP_CAP) * (size_t)pl.group_cap;
+            end = pl.ff_glist_off + sizeof(int32_t) * (1 + (size_t)FF_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.group_cap;
             if (end > pl.bytes) return "group lists beyond the workspace";
         }
     }

@@ -176,7 +176,8 @@ def test_farfield_mode_validation(lib):
     # mode on the regular grid holds too (its far-field re-check stage; its exact-only form does
     # not), a record of 40 + 3 x 24 doubles per 64 x 32-ray patch (expansion, bound terms, near
     # lenses), a 256-byte slot for the ray kernel's patch counter, and per group of 4 x 4
-    # super-patches a record of 36 doubles and a list of 1 + 16384 lens indices
+    # super-patches, for each of the 4 blocks that scan its lenses, a record of 36 doubles and a
+    # list of 1 + 4096 lens indices
     mixed = api.workspace_bytes(s.params, s.n_lens, "mixed")
     ff = lib.rs_workspace_bytes(ctypes.byref(c), s.n_lens)
     exact = lib.rs_workspace_bytes(ctypes.byref(api.to_params(s.params, "mixed", exact_recheck=True)), s.n_lens)
@@ -185,7 +186,7 @@ def test_farfield_mode_validation(lib):
     n_group = 1 * 2                       # 4 x 8 super-patches
     rec_bytes = (40 + 3 * 24) * 8
     a256 = lambda b: -(-b // 256) * 256
-    assert ff == mixed + a256(n_patch * rec_bytes) + 256 + a256(n_group * 36 * 8) + a256(n_group * 4 * 16385)
+    assert ff == mixed + a256(n_patch * rec_bytes) + 256 + a256(n_group * 4 * 36 * 8) + a256(n_group * 4 * 4 * 4097)
     assert ff >= exact + n_super * (36 * 8 + 4 * 4097) + n_patch * rec_bytes
     p = dict(s.params)
     p.update(random_rays=1)
