@@ -65,7 +65,7 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
     pl.n_chunks = (pl.W > 0 && pl.H > 0) ? (pl.H + rows - 1) / rows : 0;
     const int64_t rows_cap = pl.H < rows ? pl.H : rows;
     pl.queue_cap = (p->mode != RS_FP32) ? rows_cap * pl.W : 0;
-    pl.qcount_bytes = (WS_QCOUNT + 12 * (size_t)pl.n_chunks + 4 + 255) / 256 * 256;
+    pl.qcount_bytes = (WS_QCOUNT + 16 * (size_t)pl.n_chunks + 8 + 255) / 256 * 256;
     pl.bytes = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
     pl.far_recheck = p->mode == RS_MIXED && !(p->flags & RS_EXACT_RECHECK);
     if (pl.far_recheck && pl.random) {

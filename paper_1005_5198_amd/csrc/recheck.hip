@@ -177,39 +177,74 @@ __global__ __launch_bounds__(256) void recheck_exact_wave_kernel(const RecheckAr
     }
 }
 
-// Maps of several launches: after stage A, the entries it left go to the map's
-// deferred list (their marks cleared, the launch's unresolved count lowered), so
-// the exact stage, whose cost is one pass over every lens whatever the number of
-// rays, runs once per map instead of once per launch. Entries beyond the list's
-// capacity stay marked for their launch's exact stage.
+// Maps of several launches: before stage A, the entries the far-field stage left
+// (every entry, in the far-field mode) go to the map's gathered list and are
+// marked placed in the launch's queue; the rest (past the list's capacity) are
+// counted in *qleft, which stage A of this launch then reads as its live count.
+// The stages over every lens cost about one pass over the lenses per wave whatever
+// the number of rays, so running them once per map instead of once per launch
+// saves a pass per launch.
 __global__ __launch_bounds__(256) void recheck_defer_kernel(const RecheckArgs a) {
-    if (*a.qunres == 0u) return;
     const uint32_t n = *a.qcount;
     const int64_t W = a.i1 - a.i0;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
         const uint32_t q = a.queue[idx];
-        if (!(q & UNRESOLVED)) continue;
-        const uint32_t d = atomicAdd(a.dcount, 1u);
-        if (d >= (uint32_t)DEFER_CAP) continue;
-        const uint32_t rel = q & ~UNRESOLVED;
-        a.defer[2 * (int64_t)d] = a.i0 + (int64_t)(rel % (uint64_t)W);
-        a.defer[2 * (int64_t)d + 1] = a.jc0 + (int64_t)(rel / (uint64_t)W);
-        a.queue[idx] = rel;
-        atomicSub(a.qunres, 1u);
+        if (q & RESOLVED) continue;
+        // Once the list is full the count stops growing (by more than a grid's
+        // worth), so it cannot wrap however many launches feed it.
+        const uint32_t d = __hip_atomic_load(a.dcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                   (uint32_t)DEFER_CAP
+                               ? (uint32_t)DEFER_CAP
+                               : atomicAdd(a.dcount, 1u);
+        if (d >= (uint32_t)DEFER_CAP) {
+            atomicAdd(a.qleft, 1u);
+            continue;
+        }
+        a.defer[2 * (int64_t)d] = a.i0 + (int64_t)(q % (uint64_t)W);
+        a.defer[2 * (int64_t)d + 1] = a.jc0 + (int64_t)(q / (uint64_t)W);
+        a.queue[idx] = q | RESOLVED;
     }
 }
 
-// The exact stage over a map's deferred list, one wave per ray.
+// Stage A over a map's gathered list, one wave per ray; the rays it cannot place
+// are marked (i replaced by ~i) and counted for the exact stage.
+template <bool UNIT>
+__global__ __launch_bounds__(256) void recheck_fast_deferred_kernel(const RecheckArgs a) {
+    const uint32_t total = *a.dcount;
+    const uint32_t n = total < (uint32_t)DEFER_CAP ? total : (uint32_t)DEFER_CAP;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(a.counters + C_DIRECT, (unsigned long long)n);
+    const int lane = __lane_id();
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t e = wave_id; e < n; e += n_waves) {
+        const int64_t i = a.defer[2 * (int64_t)e], j = a.defer[2 * (int64_t)e + 1];
+        int code = 0;
+        const bool decided = fast_ray_wave<UNIT>(a, i, j, code);
+        if (lane == 0) {
+            if (decided) {
+                emit_ray(a, i, j, code);
+            } else {
+                a.defer[2 * (int64_t)e] = ~i;
+                atomicAdd(a.ucount, 1u);
+            }
+        }
+    }
+}
+
+// The exact stage over the gathered rays stage A marked, one wave per ray.
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_exact_deferred_kernel(const RecheckArgs a) {
+    if (*a.ucount == 0u) return;
     const uint32_t total = *a.dcount;
     const uint32_t n = total < (uint32_t)DEFER_CAP ? total : (uint32_t)DEFER_CAP;
     const int lane = __lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     for (uint32_t e = wave_id; e < n; e += n_waves) {
-        const int64_t i = a.defer[2 * (int64_t)e], j = a.defer[2 * (int64_t)e + 1];
+        const int64_t ii = a.defer[2 * (int64_t)e], j = a.defer[2 * (int64_t)e + 1];
+        if (ii >= 0) continue;   // placed by stage A
+        const int64_t i = ~ii;
         const int code = exact_ray_wave<UNIT>(a, i, j);
         if (lane == 0) emit_ray(a, i, j, code);
     }
@@ -433,24 +468,34 @@ hipError_t launch_recheck(const RecheckArgs &a, int64_t max_rays, bool exact_onl
     if (exact_only) {
         if (unit) hipLaunchKernelGGL(recheck_exact_kernel<true>, grid, block, 0, stream, a);
         else hipLaunchKernelGGL(recheck_exact_kernel<false>, grid, block, 0, stream, a);
-    } else if (unit) {
-        hipLaunchKernelGGL(recheck_fast_kernel<true>, grid, block, 0, stream, a);
-        hipLaunchKernelGGL(recheck_fast_wave_kernel<true>, grid, block, 0, stream, a);
-        if (a.defer) hipLaunchKernelGGL(recheck_defer_kernel, grid, block, 0, stream, a);
-        hipLaunchKernelGGL(recheck_exact_wave_kernel<true>, grid, block, 0, stream, a);
     } else {
-        hipLaunchKernelGGL(recheck_fast_kernel<false>, grid, block, 0, stream, a);
-        hipLaunchKernelGGL(recheck_fast_wave_kernel<false>, grid, block, 0, stream, a);
-        if (a.defer) hipLaunchKernelGGL(recheck_defer_kernel, grid, block, 0, stream, a);
-        hipLaunchKernelGGL(recheck_exact_wave_kernel<false>, grid, block, 0, stream, a);
+        RecheckArgs b = a;
+        if (a.defer) {
+            hipLaunchKernelGGL(recheck_defer_kernel, grid, block, 0, stream, a);
+            b.qlive = a.qleft;   // stage A of this launch takes what was not gathered
+        }
+        if (unit) {
+            hipLaunchKernelGGL(recheck_fast_kernel<true>, grid, block, 0, stream, b);
+            hipLaunchKernelGGL(recheck_fast_wave_kernel<true>, grid, block, 0, stream, b);
+            hipLaunchKernelGGL(recheck_exact_wave_kernel<true>, grid, block, 0, stream, b);
+        } else {
+            hipLaunchKernelGGL(recheck_fast_kernel<false>, grid, block, 0, stream, b);
+            hipLaunchKernelGGL(recheck_fast_wave_kernel<false>, grid, block, 0, stream, b);
+            hipLaunchKernelGGL(recheck_exact_wave_kernel<false>, grid, block, 0, stream, b);
+        }
     }
     return hipGetLastError();
 }
 
 hipError_t launch_recheck_deferred(const RecheckArgs &a, hipStream_t stream) {
     const dim3 grid(1024), block(256);
-    if (a.lens_m == nullptr) hipLaunchKernelGGL(recheck_exact_deferred_kernel<true>, grid, block, 0, stream, a);
-    else hipLaunchKernelGGL(recheck_exact_deferred_kernel<false>, grid, block, 0, stream, a);
+    if (a.lens_m == nullptr) {
+        hipLaunchKernelGGL(recheck_fast_deferred_kernel<true>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL(recheck_exact_deferred_kernel<true>, grid, block, 0, stream, a);
+    } else {
+        hipLaunchKernelGGL(recheck_fast_deferred_kernel<false>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL(recheck_exact_deferred_kernel<false>, grid, block, 0, stream, a);
+    }
     return hipGetLastError();
 }
 

@@ -26,9 +26,10 @@ constexpr int NEAR_MAX = 64;                  // per-block list of lenses close 
 constexpr size_t WS_COUNTERS = 0;             // uint64 [8]: in, out, singular, rechecked, spare
 constexpr size_t WS_QCOUNT = 64;              // uint32 [n_chunks] each: queue lengths, live counts, unresolved counts
 constexpr int64_t CHUNK_RAYS = int64_t(1) << 27;  // rays per launch (queue capacity)
-// Maps of several launches: rays that need the exact stage are gathered (as
-// (i, j) pairs) into one list of this capacity and run together after the last
-// launch; beyond it they run with their own launch's exact stage.
+// Maps of several launches: the rays a launch's first re-check stage leaves are
+// gathered (as (i, j) pairs) into one list of this capacity, and the stages over
+// every lens run on it once, after the last launch; beyond it, rays stay with
+// their own launch's stages.
 constexpr int64_t DEFER_CAP = 65536;
 
 enum Counter { C_IN = 0, C_OUT = 1, C_SING = 2, C_RECHECK = 3, C_DIRECT = 4 };

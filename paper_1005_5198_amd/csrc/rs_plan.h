@@ -17,9 +17,10 @@ struct Plan {
     int64_t W = 0, H = 0;
     int64_t rows_per_chunk = 0, n_chunks = 0;
     int64_t queue_cap = 0;   // uint32 entries (mixed only)
-    size_t qcount_bytes = 0; // WS_QCOUNT + 12 * n_chunks + 4 (queue lengths, live and unresolved counts, the
-                             // deferred count), 256-aligned
-    bool defer = false;      // several launches: exact-stage rays gathered and run after the last one
+    size_t qcount_bytes = 0; // WS_QCOUNT + 16 * n_chunks + 8 (per launch: queue length, live, unresolved and
+                             // left-after-gathering counts; the gathered and gathered-unresolved counts),
+                             // 256-aligned
+    bool defer = false;      // several launches: rays for the stages over every lens gathered, run after the last
     size_t defer_off = 0;    // int64 [DEFER_CAP][2]: (i, j) of the gathered rays
     bool far_recheck = false; // mixed mode: far-field re-check stage first
     int64_t rand_sbx = 0, rand_sby = 0; // random rays: super-patch grid of the whole rectangle

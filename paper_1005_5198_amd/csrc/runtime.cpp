@@ -165,7 +165,7 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
 
     const bool accumulate = (p->flags & RS_ACCUMULATE) != 0;
     hipError_t e =
-        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 3 * pl.n_chunks + 1, stream);
+        launch_fill((map && !accumulate) ? map : nullptr, p->npx * p->npy, workspace, 4 * pl.n_chunks + 2, stream);
     if (e != hipSuccess) return hip_fail(e, "fill kernel");
 
     char *ws = static_cast<char *>(workspace);
@@ -224,7 +224,8 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
     r.seed = p->seed;
     if (pl.defer) {
         r.defer = reinterpret_cast<int64_t *>(ws + pl.defer_off);
-        r.dcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 3 * pl.n_chunks;
+        r.dcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 4 * pl.n_chunks;
+        r.ucount = r.dcount + 1;
     }
     if (pl.random) {
         a.random = 1;
@@ -311,6 +312,7 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
             r.qcount = a.qcount;
             r.qlive = nullptr;
             r.qunres = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 2 * pl.n_chunks + c;
+            if (pl.defer) r.qleft = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 3 * pl.n_chunks + c;
             if (pl.far_recheck) {
                 uint32_t *qlive = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + pl.n_chunks + c;
                 e = launch_recheck_far(a, qlive, (a.jc1 - a.jc0) * pl.W, stream);

@@ -60,8 +60,8 @@ std::string check(const rs_map_params &p, const Plan &pl) {
         if (pl.queue_cap < rows_cap * W) return "queue below a launch's rays";
         if (rows_cap * W - 1 >= (int64_t(1) << 30)) return "queue index reaches the mark bits";
     }
-    // per launch: queue length, live and unresolved counts; then the deferred count
-    if (pl.qcount_bytes < WS_QCOUNT + 12 * (size_t)pl.n_chunks + 4 || pl.qcount_bytes % 256) return "qcount area";
+    // per launch: queue length, live, unresolved and left counts; then the gathered counts
+    if (pl.qcount_bytes < WS_QCOUNT + 16 * (size_t)pl.n_chunks + 8 || pl.qcount_bytes % 256) return "qcount area";
     size_t end = pl.qcount_bytes + 4 * (size_t)pl.queue_cap;
     if (end > pl.bytes) return "queue beyond the workspace";
     if (pl.super_cap > 0) {
