@@ -104,7 +104,7 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
     if (p->mode != RS_FP32 && !(p->flags & RS_EXACT_RECHECK) && pl.n_chunks > 1) {
         pl.defer = true;
         pl.defer_off = a256(pl.bytes);
-        pl.bytes = pl.defer_off + sizeof(int64_t) * 2 * (size_t)DEFER_CAP;
+        pl.bytes = pl.defer_off + 2 * sizeof(int64_t) * 2 * (size_t)DEFER_CAP;
     }
     if (pl.random && pl.n_chunks > 0) {
         pl.rays_cap = rows_cap * pl.W;

@@ -208,7 +208,8 @@ __global__ __launch_bounds__(256) void recheck_defer_kernel(const RecheckArgs a)
 }
 
 // Stage A over a map's gathered list, one wave per ray; the rays it cannot place
-// are marked (i replaced by ~i) and counted for the exact stage.
+// go to a list of their own, so that the exact stage deals them out one per wave
+// (marked in place, two of them could fall to one wave and its time would double).
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_fast_deferred_kernel(const RecheckArgs a) {
     const uint32_t total = *a.dcount;
@@ -225,26 +226,23 @@ __global__ __launch_bounds__(256) void recheck_fast_deferred_kernel(const Rechec
             if (decided) {
                 emit_ray(a, i, j, code);
             } else {
-                a.defer[2 * (int64_t)e] = ~i;
-                atomicAdd(a.ucount, 1u);
+                const uint32_t u = atomicAdd(a.ucount, 1u);   // u < n <= DEFER_CAP
+                a.udefer[2 * (int64_t)u] = i;
+                a.udefer[2 * (int64_t)u + 1] = j;
             }
         }
     }
 }
 
-// The exact stage over the gathered rays stage A marked, one wave per ray.
+// The exact stage over the gathered rays stage A left, one wave per ray.
 template <bool UNIT>
 __global__ __launch_bounds__(256) void recheck_exact_deferred_kernel(const RecheckArgs a) {
-    if (*a.ucount == 0u) return;
-    const uint32_t total = *a.dcount;
-    const uint32_t n = total < (uint32_t)DEFER_CAP ? total : (uint32_t)DEFER_CAP;
+    const uint32_t n = *a.ucount;
     const int lane = __lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     for (uint32_t e = wave_id; e < n; e += n_waves) {
-        const int64_t ii = a.defer[2 * (int64_t)e], j = a.defer[2 * (int64_t)e + 1];
-        if (ii >= 0) continue;   // placed by stage A
-        const int64_t i = ~ii;
+        const int64_t i = a.udefer[2 * (int64_t)e], j = a.udefer[2 * (int64_t)e + 1];
         const int code = exact_ray_wave<UNIT>(a, i, j);
         if (lane == 0) emit_ray(a, i, j, code);
     }

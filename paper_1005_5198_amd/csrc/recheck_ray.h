@@ -169,8 +169,9 @@ __device__ inline int exact_ray_wave(const RecheckArgs &a, int64_t i, int64_t j)
                 const double2 tn = term(64 * (c + 1) + lane, SX[s], SY[s], SM[s]);
                 load(64 * (c + 1 + P) + lane, SX[s], SY[s], SM[s]);
                 const double2 *T = terms[w][c & 1];
-                // in lens order, four terms read ahead of their additions
-                constexpr int B = 4;
+                // in lens order, eight terms read ahead of their additions (LDS latency
+                // is several times one addition's)
+                constexpr int B = 8;
                 double2 cur[B];
 #pragma unroll
                 for (int l = 0; l < B; ++l) cur[l] = T[l];

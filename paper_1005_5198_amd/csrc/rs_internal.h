@@ -91,10 +91,10 @@ struct RecheckArgs {
     uint32_t *qunres;      // entries stage A left to the exact stage (counted by stage A), or nullptr
     int32_t random;        // Philox-random ray positions (RS_RANDOM_RAYS)
     uint64_t seed;
-    int64_t *defer;        // (i, j) pairs gathered for the stages over every lens after the last launch
-                           // (i replaced by ~i when stage A leaves the ray to the exact stage), or nullptr
+    int64_t *defer;        // (i, j) pairs gathered for the stages over every lens after the last launch, or nullptr
     uint32_t *dcount;      // their count (may exceed DEFER_CAP: the rest stayed with their launch)
-    uint32_t *ucount;      // gathered rays stage A left to the exact stage
+    int64_t *udefer;       // (i, j) pairs of the gathered rays stage A left to the exact stage (DEFER_CAP)
+    uint32_t *ucount;      // their count
     uint32_t *qleft;       // this launch's live entries that were not gathered
 };
 

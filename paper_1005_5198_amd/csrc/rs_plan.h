@@ -21,7 +21,7 @@ struct Plan {
                              // left-after-gathering counts; the gathered and gathered-unresolved counts),
                              // 256-aligned
     bool defer = false;      // several launches: rays for the stages over every lens gathered, run after the last
-    size_t defer_off = 0;    // int64 [DEFER_CAP][2]: (i, j) of the gathered rays
+    size_t defer_off = 0;    // int64 [2][DEFER_CAP][2]: (i, j) of the gathered rays, then of those stage A left
     bool far_recheck = false; // mixed mode: far-field re-check stage first
     int64_t rand_sbx = 0, rand_sby = 0; // random rays: super-patch grid of the whole rectangle
     // Random rays: bin arrays for the largest number of bins of a launch, and

@@ -225,6 +225,7 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
     if (pl.defer) {
         r.defer = reinterpret_cast<int64_t *>(ws + pl.defer_off);
         r.dcount = reinterpret_cast<uint32_t *>(ws + WS_QCOUNT) + 4 * pl.n_chunks;
+        r.udefer = r.defer + 2 * DEFER_CAP;
         r.ucount = r.dcount + 1;
     }
     if (pl.random) {

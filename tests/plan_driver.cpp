@@ -95,7 +95,7 @@ std::string check(const rs_map_params &p, const Plan &pl) {
     if (pl.defer != want_defer) return "deferred list";
     if (pl.defer) {
         if (pl.defer_off % 256 || pl.defer_off < end) return "deferred list offset";
-        end = pl.defer_off + sizeof(int64_t) * 2 * (size_t)DEFER_CAP;
+        end = pl.defer_off + 2 * sizeof(int64_t) * 2 * (size_t)DEFER_CAP;
         if (end > pl.bytes) return "deferred list beyond the workspace";
     }
     if (pl.random && pl.n_chunks > 0) {
