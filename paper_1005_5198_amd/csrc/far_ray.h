@@ -24,6 +24,17 @@ __device__ __forceinline__ double rcp64(double r2) {
     return __builtin_fma(rc, e, rc);
 }
 
+// 1/sqrt(x) for normal positive x: v_rsq_f64 and two Newton steps
+// y <- y + y (1/2 - (x/2) y^2).
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    double e = __builtin_fma(-hx * y, y, 0.5);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-hx * y, y, 0.5);
+    return __builtin_fma(y, e, y);
+}
+
 // Geometry of super-patch sp: centre and half-diagonal (one ray spacing of
 // slack on each side), of the full box even where the window clips it.
 __device__ __forceinline__ void super_geometry(const ShootArgs &a, int64_t sp, double &cx, double &cy, double &H) {

@@ -70,13 +70,17 @@ struct FarAcc {
             c1[n] += p1;
             c2[n] += p2;
         }
-        const double ad = sqrt(r2);
-        const double am = fabs(m);
-        const double rho = h / ad;
+        // Bound terms from 1/|d| and 1/(1 - rho) (Newton-refined, within a few units of
+        // 2^-53 relative; the decision's final factor 1.001 covers that): |m|/(|d| - h)
+        // is |m|/|d| / (1 - rho).
+        const double inv_ad = rsq64(r2);
+        const double s = fabs(m) * inv_ad;
+        const double rho = h * inv_ad;
         const double rho2 = rho * rho, rho4 = rho2 * rho2, rho8 = rho4 * rho4, rho16 = rho8 * rho8;
-        sfar += am / ad;
-        trunc += am / ad * rho16 / (1.0 - rho);
-        sdef += am * 1.4142135623730951 / (ad - h);
+        const double g = rcp64(1.0 - rho);
+        sfar += s;
+        trunc += s * rho16 * g;
+        sdef += 1.4142135623730951 * s * g;
         nfar += 1.0;
     }
     // Sum over the wave's lanes (butterfly): every lane ends with the totals.
@@ -151,11 +155,18 @@ __device__ __forceinline__ void build_level(const ShootArgs &a, double cx, doubl
     __syncthreads();
     FarAcc acc;
     acc.zero();
+    // The next candidate's lens is loaded before this one is expanded, so its
+    // memory latency overlaps the expansion.
+    int64_t kn = 0;
+    double Xn = 0.0, Yn = 0.0;
+    bool vn = (int64_t)threadIdx.x < n_cand && cand(threadIdx.x, kn, Xn, Yn);
 #pragma unroll 1
     for (int64_t q = threadIdx.x; q < n_cand; q += THREADS) {
-        int64_t k;
-        double X, Y;
-        if (!cand(q, k, X, Y)) continue;
+        const int64_t k = kn;
+        const double X = Xn, Y = Yn;
+        const bool v = vn;
+        vn = q + THREADS < n_cand && cand(q + THREADS, kn, Xn, Yn);
+        if (!v) continue;
         const double d1 = cx - X, d2 = cy - Y;
         const double r2 = d1 * d1 + d2 * d2;
         if (!(r2 >= near_r2)) {
@@ -307,7 +318,7 @@ __device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, i
 // Far-field mode, level 0: group_parts(N) blocks per group, each over its range of
 // lens indices.
 template <bool UNIT>
-__global__ __launch_bounds__(FAR_GROUP_THREADS) void farfield_group_kernel(const ShootArgs a) {
+__global__ __launch_bounds__(FAR_GROUP_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void farfield_group_kernel(const ShootArgs a) {
     __shared__ FarLevelSmem<FAR_GROUP_THREADS> sm;
     const int used = group_parts(a.n_lens);
     const int64_t g = blockIdx.x / used;
