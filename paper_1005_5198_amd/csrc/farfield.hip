@@ -266,13 +266,32 @@ __device__ __forceinline__ int64_t group_of(const ShootArgs &a, int64_t sp) {
     return ((sp / a.ff_sbx) / FF_GROUP) * a.ff_gbx + (sp % a.ff_sbx) / FF_GROUP;
 }
 
-// A super-patch's candidates: its group's lists (one per part, in part order), or,
-// when one of them overflowed, every lens the group did not expand (the same test
-// it made).
+// Far-field mode with tops: top t of FF_TOP x FF_TOP groups, the same construction one
+// level up (its box holds its groups' boxes).
+__device__ __forceinline__ void top_geometry(const ShootArgs &a, int64_t t, double &cx, double &cy, double &H) {
+    constexpr int TX = FF_TOP * FF_GROUP * FF_SP_X * PATCH_X, TY = FF_TOP * FF_GROUP * FF_SP_Y * PATCH_Y;
+    const int64_t tx = t % a.ff_tbx, ty = t / a.ff_tbx;
+    const int64_t i_t = a.ff_i0 + tx * TX;
+    const int64_t j_t = a.ff_j0 + ty * TY;
+    cx = a.sx0 + ((double)i_t + 0.5 * TX) * a.spx;
+    cy = a.sy0 + ((double)j_t + 0.5 * TY) * a.spy;
+    const double hx = (0.5 * TX + 1.0) * a.spx;
+    const double hy = (0.5 * TY + 1.0) * a.spy;
+    H = sqrt(hx * hx + hy * hy) * (1.0 + 1e-12);
+}
+
+__device__ __forceinline__ int64_t top_of(const ShootArgs &a, int64_t g) {
+    return ((g / a.ff_gbx) / FF_TOP) * a.ff_tbx + (g % a.ff_gbx) / FF_TOP;
+}
+
+// A level's candidates: the lists of the level above (one per part, in part order), or,
+// when one of them overflowed, every lens that level did not expand (the same test it
+// made).
 struct ListCandidates {
     static_assert(FF_GROUP_PARTS == 4, "three part ends below");
     const double *xy;
-    const global_i32 *lists;   // the parts' lists, 1 + FF_PART_CAP apart
+    const global_i32 *lists;   // the parts' lists, stride apart
+    int64_t stride;
     int64_t e0, e1, e2;        // candidates before the end of parts 0, 1, 2
     bool scan_all;
     double cx, cy, r2;
@@ -283,7 +302,7 @@ struct ListCandidates {
             const int64_t a0 = q >= e0, a1 = q >= e1, a2 = q >= e2;
             const int64_t part = a0 + a1 + a2;
             const int64_t before = a0 * e0 + a1 * (e1 - e0) + a2 * (e2 - e1);
-            k = (int64_t)lists[part * (1 + FF_PART_CAP) + 1 + (q - before)];
+            k = (int64_t)lists[part * stride + 1 + (q - before)];
         }
         X = ((global_double *)xy)[2 * k];
         Y = ((global_double *)xy)[2 * k + 1];
@@ -295,24 +314,38 @@ struct ListCandidates {
     }
 };
 
-__device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, int64_t g, int64_t &n) {
+// Candidates from `used` lists of capacity cap, stride apart, of the level about (cx, cy)
+// with half-diagonal H.
+__device__ __forceinline__ ListCandidates list_candidates(const ShootArgs &a, const int32_t *lists, int64_t stride,
+                                                          int32_t cap, int used, double cx, double cy, double H,
+                                                          int64_t &n) {
     ListCandidates c;
     c.xy = a.lens_xy;
-    double H;
-    group_geometry(a, g, c.cx, c.cy, H);
+    c.cx = cx;
+    c.cy = cy;
     c.r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
-    c.lists = (const global_i32 *)(a.ff_glist + g * FF_GROUP_PARTS * (int64_t)(1 + FF_PART_CAP));
-    const int used = group_parts(a.n_lens);   // the parts' lists past these were not written
-    const int32_t n0 = c.lists[0];
-    const int32_t n1 = used > 1 ? c.lists[1 + FF_PART_CAP] : 0;
-    const int32_t n2 = used > 2 ? c.lists[2 * (1 + FF_PART_CAP)] : 0;
-    const int32_t n3 = used > 3 ? c.lists[3 * (1 + FF_PART_CAP)] : 0;
-    c.scan_all = n0 > FF_PART_CAP || n1 > FF_PART_CAP || n2 > FF_PART_CAP || n3 > FF_PART_CAP;
+    c.lists = (const global_i32 *)lists;
+    c.stride = stride;
+    const int32_t n0 = c.lists[0];   // the parts' lists past `used` were not written
+    const int32_t n1 = used > 1 ? c.lists[stride] : 0;
+    const int32_t n2 = used > 2 ? c.lists[2 * stride] : 0;
+    const int32_t n3 = used > 3 ? c.lists[3 * stride] : 0;
+    c.scan_all = n0 > cap || n1 > cap || n2 > cap || n3 > cap;
     c.e0 = n0;
     c.e1 = c.e0 + n1;
     c.e2 = c.e1 + n2;
     n = c.scan_all ? a.n_lens : c.e2 + n3;
     return c;
+}
+
+// A super-patch's candidates: its group's lists (one per part), or with tops the
+// group's one list.
+__device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, int64_t g, int64_t &n) {
+    double cx, cy, H;
+    group_geometry(a, g, cx, cy, H);
+    const int32_t *lists = a.ff_glist + g * FF_GROUP_PARTS * (int64_t)(1 + FF_PART_CAP);
+    if (a.ff_top) return list_candidates(a, lists, 0, FF_GROUP_ONE_CAP, 1, cx, cy, H, n);
+    return list_candidates(a, lists, 1 + FF_PART_CAP, FF_PART_CAP, group_parts(a.n_lens), cx, cy, H, n);
 }
 
 // Far-field mode, level 0: group_parts(N) blocks per group, each over its range of
@@ -333,6 +366,46 @@ __global__ __launch_bounds__(FAR_GROUP_THREADS) __attribute__((amdgpu_waves_per_
                                          a.ff_group + slot * (int64_t)FAR_REC, nullptr, 0, 0.0, 0.0, sm);
 }
 
+// Far-field mode with tops, level 0: group_parts(N) blocks per top, each over its range of
+// lens indices (the group kernel's scan one level up). A launch has few tops (a band of
+// 2^27 rays holds about 30), so the blocks are as large as they can be.
+constexpr int FAR_TOP_THREADS = 1024;
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_TOP_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void farfield_top_kernel(const ShootArgs a) {
+    __shared__ FarLevelSmem<FAR_TOP_THREADS> sm;
+    const int used = group_parts(a.n_lens);
+    const int64_t t = blockIdx.x / used;
+    const int part = (int)(blockIdx.x % used);
+    const int64_t first = a.n_lens * part / used;
+    const int64_t last = a.n_lens * (part + 1) / used;
+    double cx, cy, H;
+    top_geometry(a, t, cx, cy, H);
+    const int64_t slot = t * FF_GROUP_PARTS + part;
+    build_level<UNIT, FAR_TOP_THREADS>(a, cx, cy, H, last - first, AllLenses{a.lens_xy, first},
+                                         a.ff_tlist + slot * (int64_t)(1 + FF_TOP_PART_CAP), FF_TOP_PART_CAP,
+                                         a.ff_top + slot * (int64_t)FAR_REC, nullptr, 0, 0.0, 0.0, sm);
+}
+
+// Far-field mode with tops, level 1: one block per group, candidates from its top's
+// lists, the top's expansion re-centred and added; one record (part 0) and one list.
+template <bool UNIT>
+__global__ __launch_bounds__(FAR_GROUP_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void farfield_group_top_kernel(const ShootArgs a) {
+    __shared__ FarLevelSmem<FAR_GROUP_THREADS> sm;
+    const int64_t g = blockIdx.x;
+    const int64_t t = top_of(a, g);
+    double tcx, tcy, tH;
+    top_geometry(a, t, tcx, tcy, tH);
+    const int used = group_parts(a.n_lens);
+    int64_t n;
+    const ListCandidates c = list_candidates(a, a.ff_tlist + t * FF_GROUP_PARTS * (int64_t)(1 + FF_TOP_PART_CAP),
+                                             1 + FF_TOP_PART_CAP, FF_TOP_PART_CAP, used, tcx, tcy, tH, n);
+    double cx, cy, H;
+    group_geometry(a, g, cx, cy, H);
+    build_level<UNIT, FAR_GROUP_THREADS>(a, cx, cy, H, n, c, a.ff_glist + g * FF_GROUP_PARTS * (int64_t)(1 + FF_PART_CAP),
+                                         FF_GROUP_ONE_CAP, a.ff_group + g * FF_GROUP_PARTS * (int64_t)FAR_REC,
+                                         a.ff_top + t * FF_GROUP_PARTS * (int64_t)FAR_REC, used, tcx, tcy, sm);
+}
+
 // Far-field mode, level 1: one block per super-patch, candidates from its group,
 // the group's expansion re-centred and added.
 template <bool UNIT>
@@ -346,7 +419,7 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_group_kernel(const
     super_geometry(a, sp, cx, cy, H);
     build_level<UNIT>(a, cx, cy, H, n, c, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
                       a.ff_super + sp * (int64_t)FAR_REC, a.ff_group + g * FF_GROUP_PARTS * (int64_t)FAR_REC,
-                      group_parts(a.n_lens), c.cx, c.cy, sm);
+                      a.ff_top ? 1 : group_parts(a.n_lens), c.cx, c.cy, sm);
 }
 
 // Level 1 of every map of a mixed batch that flagged rays: one block per
@@ -769,9 +842,19 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     const dim3 block(FAR_THREADS);
     const int64_t n_group = a.ff_gbx * ((((nby + FF_SP_Y - 1) / FF_SP_Y) + FF_GROUP - 1) / FF_GROUP);
     const dim3 group_block(FAR_GROUP_THREADS);
-    const dim3 group_grid((unsigned)(n_group * group_parts(a.n_lens)));
-    if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), group_grid, group_block, 0, stream, a);
-    else hipLaunchKernelGGL((farfield_group_kernel<false>), group_grid, group_block, 0, stream, a);
+    if (a.ff_top) {
+        const int64_t n_gy = (((nby + FF_SP_Y - 1) / FF_SP_Y) + FF_GROUP - 1) / FF_GROUP;
+        const int64_t n_top = a.ff_tbx * ((n_gy + FF_TOP - 1) / FF_TOP);
+        const dim3 top_grid((unsigned)(n_top * group_parts(a.n_lens)));
+        if (unit) hipLaunchKernelGGL((farfield_top_kernel<true>), top_grid, dim3(FAR_TOP_THREADS), 0, stream, a);
+        else hipLaunchKernelGGL((farfield_top_kernel<false>), top_grid, dim3(FAR_TOP_THREADS), 0, stream, a);
+        if (unit) hipLaunchKernelGGL((farfield_group_top_kernel<true>), dim3((unsigned)n_group), group_block, 0, stream, a);
+        else hipLaunchKernelGGL((farfield_group_top_kernel<false>), dim3((unsigned)n_group), group_block, 0, stream, a);
+    } else {
+        const dim3 group_grid((unsigned)(n_group * group_parts(a.n_lens)));
+        if (unit) hipLaunchKernelGGL((farfield_group_kernel<true>), group_grid, group_block, 0, stream, a);
+        else hipLaunchKernelGGL((farfield_group_kernel<false>), group_grid, group_block, 0, stream, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (unit) hipLaunchKernelGGL((farfield_super_group_kernel<true>), dim3((unsigned)n_super), block, 0, stream, a);

@@ -51,7 +51,7 @@ int validate(const rs_map_params *p, int64_t n_lens) {
     return RS_OK;
 }
 
-Plan make_plan(const rs_map_params *p, int64_t rows_override) {
+Plan make_plan(const rs_map_params *p, int64_t n_lens, int64_t rows_override) {
     Plan pl;
     pl.W = p->i1 - p->i0;
     pl.H = p->j1 - p->j0;
@@ -98,6 +98,14 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
             off += a256(sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.group_cap);
             pl.ff_glist_off = off;
             off += a256(sizeof(int32_t) * (1 + (size_t)FF_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.group_cap);
+            if (n_lens >= FF_TOP_MIN_LENSES) {
+                const int64_t gbx = (sbx + FF_GROUP - 1) / FF_GROUP, gby = (sby + FF_GROUP - 1) / FF_GROUP;
+                pl.top_cap = ((gbx + FF_TOP - 1) / FF_TOP) * ((gby + FF_TOP - 1) / FF_TOP);
+                pl.ff_top_off = off;
+                off += a256(sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.top_cap);
+                pl.ff_tlist_off = off;
+                off += a256(sizeof(int32_t) * (1 + (size_t)FF_TOP_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.top_cap);
+            }
         }
         pl.bytes = off;
     }
@@ -133,15 +141,15 @@ Plan make_plan(const rs_map_params *p, int64_t rows_override) {
 }
 
 // (the workspace grows with the rows per launch: a binary search over bands)
-bool plan_within(const rs_map_params *p, size_t max_bytes, Plan &out) {
-    out = make_plan(p);
+bool plan_within(const rs_map_params *p, int64_t n_lens, size_t max_bytes, Plan &out) {
+    out = make_plan(p, n_lens);
     if (out.bytes <= max_bytes) return true;
     int64_t lo = 1, hi = out.rows_per_chunk / PATCH_Y - 1;   // bands per launch
-    Plan best = make_plan(p, PATCH_Y);
+    Plan best = make_plan(p, n_lens, PATCH_Y);
     if (best.bytes > max_bytes) return false;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
-        Plan t = make_plan(p, mid * PATCH_Y);
+        Plan t = make_plan(p, n_lens, mid * PATCH_Y);
         if (t.bytes <= max_bytes) {
             lo = mid;
             best = t;
@@ -149,7 +157,7 @@ bool plan_within(const rs_map_params *p, size_t max_bytes, Plan &out) {
             hi = mid - 1;
         }
     }
-    if (best.rows_per_chunk != lo * PATCH_Y) best = make_plan(p, lo * PATCH_Y);
+    if (best.rows_per_chunk != lo * PATCH_Y) best = make_plan(p, n_lens, lo * PATCH_Y);
     out = best;
     return true;
 }

@@ -40,6 +40,8 @@ struct Plan {
     // Far-field mode: group records and lists of the largest launch.
     int64_t group_cap = 0;
     size_t ff_group_off = 0, ff_glist_off = 0;
+    int64_t top_cap = 0;      // far-field mode with at least FF_TOP_MIN_LENSES lenses: tops per launch
+    size_t ff_top_off = 0, ff_tlist_off = 0;
     size_t bytes = 0;
 };
 
@@ -52,10 +54,10 @@ void random_bins(int64_t rays, double sw, double sh, int64_t &nbx, int64_t &nby)
 
 // The plan of a valid window; rows_override > 0 (a multiple of PATCH_Y) replaces
 // the default rows per launch.
-Plan make_plan(const rs_map_params *p, int64_t rows_override = 0);
+Plan make_plan(const rs_map_params *p, int64_t n_lens, int64_t rows_override = 0);
 
 // The plan with the most rows per launch (a multiple of PATCH_Y, at most the default)
 // whose workspace fits max_bytes; false when a single band of PATCH_Y rows does not fit.
-bool plan_within(const rs_map_params *p, size_t max_bytes, Plan &out);
+bool plan_within(const rs_map_params *p, int64_t n_lens, size_t max_bytes, Plan &out);
 
 }  // namespace rs

@@ -130,7 +130,7 @@ int enqueue_map(const rs_map_params *p, const double *lens_xy, const double *len
     int rc = check_inputs(p, lens_xy, lens_m, n_lens, map, pix);
     if (rc) return rc;
     if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
-    const Plan pl = make_plan(p);
+    const Plan pl = make_plan(p, n_lens);
     if (workspace_bytes < pl.bytes)
         return fail(RS_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, pl.bytes);
     return enqueue_planned(p, lens_xy, lens_m, n_lens, map, pix, workspace, stream, shape, kernel_ms, pl, true);
@@ -147,9 +147,9 @@ int enqueue_map_fixed(const rs_map_params *p, const double *lens_xy, const doubl
     if (rc) return rc;
     if (!map) return fail(RS_EINVAL, "map is NULL");
     Plan pl;
-    if (!plan_within(p, scratch_bytes, pl))
+    if (!plan_within(p, n_lens, scratch_bytes, pl))
         return fail(RS_ENOMEM, "one band of %d rows of this window needs %zu bytes of scratch; the static "
-                    "scratch holds %zu", PATCH_Y, make_plan(p, PATCH_Y).bytes, scratch_bytes);
+                    "scratch holds %zu", PATCH_Y, make_plan(p, n_lens, PATCH_Y).bytes, scratch_bytes);
     void *scratch = nullptr;
     rc = scratch_of_device(&scratch);
     if (rc) return rc;
@@ -254,6 +254,11 @@ static int enqueue_planned(const rs_map_params *p, const double *lens_xy, const 
             a.ff_gbx = (a.ff_sbx + FF_GROUP - 1) / FF_GROUP;
             a.ff_group = reinterpret_cast<double *>(ws + pl.ff_group_off);
             a.ff_glist = reinterpret_cast<int32_t *>(ws + pl.ff_glist_off);
+            if (pl.top_cap > 0) {
+                a.ff_tbx = (a.ff_gbx + FF_TOP - 1) / FF_TOP;
+                a.ff_top = reinterpret_cast<double *>(ws + pl.ff_top_off);
+                a.ff_tlist = reinterpret_cast<int32_t *>(ws + pl.ff_tlist_off);
+            }
         }
         if (pl.random) {
             a.ff_i0 = 0;
@@ -347,7 +352,7 @@ const char *rs_last_error(void) { return g_last_error.c_str(); }
 
 size_t rs_workspace_bytes(const rs_map_params *params, int64_t n_lens) {
     if (validate(params, n_lens) != RS_OK) return 0;
-    return make_plan(params).bytes;
+    return make_plan(params, n_lens).bytes;
 }
 
 int rs_make_map(const rs_map_params *params, const double *lens_xy, const double *lens_m, int64_t n_lens,

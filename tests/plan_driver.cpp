@@ -49,7 +49,7 @@ rs_map_params base(int64_t nx, int64_t ny) {
 }
 
 // Every invariant of a plan that the launch code relies on; returns the first broken one.
-std::string check(const rs_map_params &p, const Plan &pl) {
+std::string check(const rs_map_params &p, int64_t n_lens, const Plan &pl) {
     const int64_t W = p.i1 - p.i0, H = p.j1 - p.j0;
     if (pl.W != W || pl.H != H) return "window";
     if (pl.rows_per_chunk <= 0 || pl.rows_per_chunk % PATCH_Y) return "rows not whole bands";
@@ -88,6 +88,20 @@ std::string check(const rs_map_params &p, const Plan &pl) {
             if (pl.ff_glist_off % 256 || pl.ff_glist_off < end) return "group list offset";
             end = pl.ff_glist_off + sizeof(int32_t) * (1 + (size_t)FF_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.group_cap;
             if (end > pl.bytes) return "group lists beyond the workspace";
+            // tops above the groups from FF_TOP_MIN_LENSES lenses on: records, then lists
+            const int64_t gbx = (sbx + FF_GROUP - 1) / FF_GROUP, gby = (sby + FF_GROUP - 1) / FF_GROUP;
+            const int64_t tops = ((gbx + FF_TOP - 1) / FF_TOP) * ((gby + FF_TOP - 1) / FF_TOP);
+            if ((n_lens >= FF_TOP_MIN_LENSES) != (pl.top_cap > 0)) return "tops";
+            if (pl.top_cap > 0) {
+                if (pl.top_cap < tops) return "too few top records";
+                if (pl.ff_top_off % 256 || pl.ff_top_off < end) return "top record offset";
+                end = pl.ff_top_off + sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.top_cap;
+                if (pl.ff_tlist_off % 256 || pl.ff_tlist_off < end) return "top list offset";
+                end = pl.ff_tlist_off + sizeof(int32_t) * (1 + (size_t)FF_TOP_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.top_cap;
+                if (end > pl.bytes) return "top lists beyond the workspace";
+            }
+        } else if (pl.top_cap != 0) {
+            return "tops outside the far-field mode";
         }
     }
     // several launches of a mode with re-checks gather their exact-stage rays
@@ -171,45 +185,48 @@ int main() {
         const int64_t heights[] = {1, 31, 32, 33, 640, 3840, 32768};
         const int modes[] = {RS_FP32, RS_MIXED, RS_FARFIELD};
         const int flag_sets[] = {0, RS_RANDOM_RAYS, RS_EXACT_RECHECK};
+        const int64_t lens_counts[] = {100, FF_TOP_MIN_LENSES};
         const size_t caps[] = {size_t(64) << 20, size_t(8) << 20, size_t(1) << 20};
         int plans = 0, within = 0, refused = 0;
         std::string broken;
         for (int64_t W : widths)
             for (int64_t H : heights)
                 for (int m : modes)
-                    for (int f : flag_sets) {
+                    for (int f : flag_sets)
+                    for (int64_t n_lens : lens_counts) {
                         if (m == RS_FARFIELD && (f & RS_RANDOM_RAYS)) continue;
+                        if (m != RS_FARFIELD && n_lens != 100) continue;   // only the far-field plan depends on it
                         if ((double)W * (double)H > 3e9) continue;   // keep the table quick
                         rs_map_params p = base(W, H + 5);
                         p.j0 = 5;
                         p.j1 = H + 5;
                         p.mode = m;
                         p.flags = f;
-                        if (validate(&p, 100) != RS_OK) {
+                        if (validate(&p, n_lens) != RS_OK) {
                             broken += "\"invalid " + std::to_string(W) + "x" + std::to_string(H) + "\",";
                             continue;
                         }
-                        const Plan pl = make_plan(&p);
+                        const Plan pl = make_plan(&p, n_lens);
                         ++plans;
-                        std::string e = check(p, pl);
+                        std::string e = check(p, n_lens, pl);
                         if (!e.empty())
                             broken += "\"" + e + " " + std::to_string(W) + "x" + std::to_string(H) + " m" +
                                       std::to_string(m) + " f" + std::to_string(f) + "\",";
                         for (size_t cap : caps) {
                             Plan pc;
-                            if (!plan_within(&p, cap, pc)) {
+                            if (!plan_within(&p, n_lens, cap, pc)) {
                                 ++refused;
                                 // refused only when one band does not fit
-                                if (make_plan(&p, PATCH_Y).bytes <= cap) broken += "\"refused a fitting window\",";
+                                if (make_plan(&p, n_lens, PATCH_Y).bytes <= cap) broken += "\"refused a fitting window\",";
                                 continue;
                             }
                             ++within;
-                            e = check(p, pc);
+                            e = check(p, n_lens, pc);
                             if (!e.empty() || pc.bytes > cap || pc.rows_per_chunk > pl.rows_per_chunk)
                                 broken += "\"within " + e + " " + std::to_string(W) + "x" + std::to_string(H) + "\",";
                             // the most rows that fit: one more band would not (unless the whole window fits)
                             if (pc.rows_per_chunk < pl.rows_per_chunk && pc.rows_per_chunk < H &&
-                                make_plan(&p, pc.rows_per_chunk + PATCH_Y).bytes <= cap)
+                                make_plan(&p, n_lens, pc.rows_per_chunk + PATCH_Y).bytes <= cap)
                                 broken += "\"not the largest fitting band count\",";
                         }
                     }
@@ -227,11 +244,11 @@ int main() {
         p.sw = 240.0;
         p.sy0 = -24.0;
         p.sh = 48.0;
-        const Plan pl = make_plan(&p);
+        const Plan pl = make_plan(&p, 17240);
         put("c2_chunks", std::to_string(pl.n_chunks));
         put("c2_bytes", std::to_string(pl.bytes));
         Plan pc;
-        const bool ok = plan_within(&p, size_t(64) << 20, pc);
+        const bool ok = plan_within(&p, 17240, size_t(64) << 20, pc);
         put("c2_scratch_chunks", std::to_string(ok ? pc.n_chunks : -1));
         put("c2_scratch_rows", std::to_string(ok ? pc.rows_per_chunk : -1));
     }

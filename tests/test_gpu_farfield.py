@@ -100,6 +100,35 @@ def test_farfield_list_overflows(rs):
     say(f"  re-checked {st['rays_rechecked']}")
 
 
+def test_farfield_tops(rs):
+    """140000 lenses (tops of 4 x 4 groups above the groups) of masses +1 and -1 in a disc of
+    radius 1500 around the config-0 grid: most lenses lie beyond four half-diagonals of the
+    window's top and enter through its expansion, re-centred three times down to the patch."""
+    rng = np.random.default_rng(27)
+    s = w.config0()
+    n = 140000
+    lenses = w.lenses_in_disc(n, 1500.0, rng)
+    masses = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    sub = w.MapSpec("tops", s.params, lenses, masses).window(448, 576, 480, 544)
+    st = check_exact(rs, sub)
+    say(f"  re-checked {st['rays_rechecked']}")
+
+
+def test_farfield_top_list_overflows(rs):
+    """140000 lenses of masses +1 and -1 in a disc of radius 40: every lens lies within four
+    half-diagonals of the window's top, so its four part lists (35000 lenses each) overflow and
+    the group scans every lens against the top's test; the group's list and the levels below
+    overflow in turn."""
+    rng = np.random.default_rng(26)
+    s = w.config0()
+    n = 140000
+    lenses = w.lenses_in_disc(n, 40.0, rng)
+    masses = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    sub = w.MapSpec("top overflows", s.params, lenses, masses).window(448, 512, 480, 512)
+    st = check_exact(rs, sub)
+    say(f"  re-checked {st['rays_rechecked']}")
+
+
 def test_farfield_config2_full_equals_mixed(rs):
     """The full 19200 x 3840-ray map: the far-field map equals the mixed-mode map (itself the
     oracle's, see the parity tests), and sampled rays equal the oracle's one by one."""
