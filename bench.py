@@ -41,9 +41,9 @@ METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batch
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB copy), from the counters in
 # profiles/shoot_kernel_config2.md, taken with the kernel sources whose digest follows. When any
 # of those sources differs, the figure no longer describes the kernel and is reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = 1.478e9
+TRAFFIC_BYTES_PER_LAUNCH = 1.482e9
 TRAFFIC_SOURCES = ("shoot.hip", "shoot_common.h", "rs_internal.h", "rs_layout.h")
-TRAFFIC_SOURCES_DIGEST = "0918e2b05ff9c1fe"
+TRAFFIC_SOURCES_DIGEST = "acad4b43f7edcd86"
 
 
 def kernel_sources_digest() -> str:
