@@ -42,8 +42,8 @@ METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batch
 # profiles/shoot_kernel_config2.md, taken with the kernel sources whose digest follows. When any
 # of those sources differs, the figure no longer describes the kernel and is reported as null.
 TRAFFIC_BYTES_PER_LAUNCH = 1.482e9
-TRAFFIC_SOURCES = ("shoot.hip", "shoot_common.h", "rs_internal.h", "rs_layout.h")
-TRAFFIC_SOURCES_DIGEST = "acad4b43f7edcd86"
+TRAFFIC_SOURCES = ("shoot.hip", "shoot_common.h", "recheck_ray.h", "philox.h", "rs_internal.h", "rs_layout.h")
+TRAFFIC_SOURCES_DIGEST = "4034070a1a4e144a"
 
 
 def kernel_sources_digest() -> str:
