@@ -42,14 +42,16 @@ METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batch
 # profiles/shoot_kernel_config2.md, taken with the kernel sources whose digest follows. When any
 # of those sources differs, the figure no longer describes the kernel and is reported as null.
 TRAFFIC_BYTES_PER_LAUNCH = 1.482e9
-TRAFFIC_SOURCES = ("shoot.hip", "shoot_common.h", "recheck_ray.h", "philox.h", "rs_internal.h", "rs_layout.h")
-TRAFFIC_SOURCES_DIGEST = "4034070a1a4e144a"
+TRAFFIC_SOURCES = tuple(os.path.join("paper_1005_5198_amd", "csrc", f) for f in (
+    "shoot.hip", "shoot_common.h", "recheck_ray.h", "philox.h", "rs_internal.h", "rs_layout.h")) + (
+    os.path.join("include", "rayshoot.h"),)
+TRAFFIC_SOURCES_DIGEST = "4e96e4887040bab1"
 
 
 def kernel_sources_digest() -> str:
     h = hashlib.sha256()
     for name in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1005_5198_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
