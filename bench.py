@@ -41,11 +41,11 @@ METRIC = "ray·lens interactions/s (%FP32 peak); maps/s + p50/p99 latency, batch
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB copy), from the counters in
 # profiles/shoot_kernel_config2.md, taken with the kernel sources whose digest follows. When any
 # of those sources differs, the figure no longer describes the kernel and is reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = 1.482e9
+TRAFFIC_BYTES_PER_LAUNCH = 1.480e9
 TRAFFIC_SOURCES = tuple(os.path.join("paper_1005_5198_amd", "csrc", f) for f in (
     "shoot.hip", "shoot_common.h", "recheck_ray.h", "philox.h", "rs_internal.h", "rs_layout.h")) + (
     os.path.join("include", "rayshoot.h"),)
-TRAFFIC_SOURCES_DIGEST = "4e96e4887040bab1"
+TRAFFIC_SOURCES_DIGEST = "dabdd5d46d8c4c59"
 
 
 def kernel_sources_digest() -> str:

@@ -287,21 +287,27 @@ __device__ __forceinline__ int64_t top_of(const ShootArgs &a, int64_t g) {
 // A level's candidates: the lists of the level above (one per part, in part order), or,
 // when one of them overflowed, every lens that level did not expand (the same test it
 // made).
+template <int P>
 struct ListCandidates {
-    static_assert(FF_GROUP_PARTS == 4, "three part ends below");
     const double *xy;
     const global_i32 *lists;   // the parts' lists, stride apart
     int64_t stride;
-    int64_t e0, e1, e2;        // candidates before the end of parts 0, 1, 2
+    int64_t e[P - 1];          // candidates before the end of parts 0 .. P - 2 (non-decreasing)
     bool scan_all;
     double cx, cy, r2;
     __device__ bool operator()(int64_t q, int64_t &k, double &X, double &Y) const {
         if (scan_all) {
             k = q;
         } else {
-            const int64_t a0 = q >= e0, a1 = q >= e1, a2 = q >= e2;
-            const int64_t part = a0 + a1 + a2;
-            const int64_t before = a0 * e0 + a1 * (e1 - e0) + a2 * (e2 - e1);
+            // q's part is the number of part ends at or below q; its offset counts from the
+            // last of them (unrolled, so e stays in registers)
+            int64_t part = 0, before = 0;
+#pragma unroll
+            for (int i = 0; i < P - 1; ++i) {
+                const bool past = q >= e[i];
+                part += past;
+                before = past ? e[i] : before;
+            }
             k = (int64_t)lists[part * stride + 1 + (q - before)];
         }
         X = ((global_double *)xy)[2 * k];
@@ -316,36 +322,39 @@ struct ListCandidates {
 
 // Candidates from `used` lists of capacity cap, stride apart, of the level about (cx, cy)
 // with half-diagonal H.
-__device__ __forceinline__ ListCandidates list_candidates(const ShootArgs &a, const int32_t *lists, int64_t stride,
-                                                          int32_t cap, int used, double cx, double cy, double H,
-                                                          int64_t &n) {
-    ListCandidates c;
+template <int P>
+__device__ __forceinline__ ListCandidates<P> list_candidates(const ShootArgs &a, const int32_t *lists, int64_t stride,
+                                                             int32_t cap, int used, double cx, double cy, double H,
+                                                             int64_t &n) {
+    ListCandidates<P> c;
     c.xy = a.lens_xy;
     c.cx = cx;
     c.cy = cy;
     c.r2 = (FAR_RATIO * H) * (FAR_RATIO * H);
     c.lists = (const global_i32 *)lists;
     c.stride = stride;
-    const int32_t n0 = c.lists[0];   // the parts' lists past `used` were not written
-    const int32_t n1 = used > 1 ? c.lists[stride] : 0;
-    const int32_t n2 = used > 2 ? c.lists[2 * stride] : 0;
-    const int32_t n3 = used > 3 ? c.lists[3 * stride] : 0;
-    c.scan_all = n0 > cap || n1 > cap || n2 > cap || n3 > cap;
-    c.e0 = n0;
-    c.e1 = c.e0 + n1;
-    c.e2 = c.e1 + n2;
-    n = c.scan_all ? a.n_lens : c.e2 + n3;
+    c.scan_all = false;
+    int64_t total = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int32_t np = p < used ? c.lists[p * stride] : 0;   // the lists past `used` were not written
+        c.scan_all = c.scan_all || np > cap;
+        total += np;
+        if (p < P - 1) c.e[p] = total;
+    }
+    n = c.scan_all ? a.n_lens : total;
     return c;
 }
 
 // A super-patch's candidates: its group's lists (one per part), or with tops the
 // group's one list.
-__device__ __forceinline__ ListCandidates group_candidates(const ShootArgs &a, int64_t g, int64_t &n) {
+__device__ __forceinline__ ListCandidates<FF_GROUP_PARTS> group_candidates(const ShootArgs &a, int64_t g, int64_t &n) {
     double cx, cy, H;
     group_geometry(a, g, cx, cy, H);
     const int32_t *lists = a.ff_glist + g * FF_GROUP_PARTS * (int64_t)(1 + FF_PART_CAP);
-    if (a.ff_top) return list_candidates(a, lists, 0, FF_GROUP_ONE_CAP, 1, cx, cy, H, n);
-    return list_candidates(a, lists, 1 + FF_PART_CAP, FF_PART_CAP, group_parts(a.n_lens), cx, cy, H, n);
+    if (a.ff_top) return list_candidates<FF_GROUP_PARTS>(a, lists, 0, FF_GROUP_ONE_CAP, 1, cx, cy, H, n);
+    return list_candidates<FF_GROUP_PARTS>(a, lists, 1 + FF_PART_CAP, FF_PART_CAP, group_parts(a.n_lens), cx, cy,
+                                           H, n);
 }
 
 // Far-field mode, level 0: group_parts(N) blocks per group, each over its range of
@@ -366,21 +375,20 @@ __global__ __launch_bounds__(FAR_GROUP_THREADS) __attribute__((amdgpu_waves_per_
                                          a.ff_group + slot * (int64_t)FAR_REC, nullptr, 0, 0.0, 0.0, sm);
 }
 
-// Far-field mode with tops, level 0: group_parts(N) blocks per top, each over its range of
+// Far-field mode with tops, level 0: FF_TOP_PARTS blocks per top, each over its range of
 // lens indices (the group kernel's scan one level up). A launch has few tops (a band of
 // 2^27 rays holds about 30), so the blocks are as large as they can be.
 constexpr int FAR_TOP_THREADS = 1024;
 template <bool UNIT>
 __global__ __launch_bounds__(FAR_TOP_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void farfield_top_kernel(const ShootArgs a) {
     __shared__ FarLevelSmem<FAR_TOP_THREADS> sm;
-    const int used = group_parts(a.n_lens);
-    const int64_t t = blockIdx.x / used;
-    const int part = (int)(blockIdx.x % used);
-    const int64_t first = a.n_lens * part / used;
-    const int64_t last = a.n_lens * (part + 1) / used;
+    const int64_t t = blockIdx.x / FF_TOP_PARTS;
+    const int part = (int)(blockIdx.x % FF_TOP_PARTS);
+    const int64_t first = a.n_lens * part / FF_TOP_PARTS;
+    const int64_t last = a.n_lens * (part + 1) / FF_TOP_PARTS;
     double cx, cy, H;
     top_geometry(a, t, cx, cy, H);
-    const int64_t slot = t * FF_GROUP_PARTS + part;
+    const int64_t slot = t * FF_TOP_PARTS + part;
     build_level<UNIT, FAR_TOP_THREADS>(a, cx, cy, H, last - first, AllLenses{a.lens_xy, first},
                                          a.ff_tlist + slot * (int64_t)(1 + FF_TOP_PART_CAP), FF_TOP_PART_CAP,
                                          a.ff_top + slot * (int64_t)FAR_REC, nullptr, 0, 0.0, 0.0, sm);
@@ -395,15 +403,15 @@ __global__ __launch_bounds__(FAR_GROUP_THREADS) __attribute__((amdgpu_waves_per_
     const int64_t t = top_of(a, g);
     double tcx, tcy, tH;
     top_geometry(a, t, tcx, tcy, tH);
-    const int used = group_parts(a.n_lens);
     int64_t n;
-    const ListCandidates c = list_candidates(a, a.ff_tlist + t * FF_GROUP_PARTS * (int64_t)(1 + FF_TOP_PART_CAP),
-                                             1 + FF_TOP_PART_CAP, FF_TOP_PART_CAP, used, tcx, tcy, tH, n);
+    const ListCandidates<FF_TOP_PARTS> c =
+        list_candidates<FF_TOP_PARTS>(a, a.ff_tlist + t * FF_TOP_PARTS * (int64_t)(1 + FF_TOP_PART_CAP),
+                                      1 + FF_TOP_PART_CAP, FF_TOP_PART_CAP, FF_TOP_PARTS, tcx, tcy, tH, n);
     double cx, cy, H;
     group_geometry(a, g, cx, cy, H);
     build_level<UNIT, FAR_GROUP_THREADS>(a, cx, cy, H, n, c, a.ff_glist + g * FF_GROUP_PARTS * (int64_t)(1 + FF_PART_CAP),
                                          FF_GROUP_ONE_CAP, a.ff_group + g * FF_GROUP_PARTS * (int64_t)FAR_REC,
-                                         a.ff_top + t * FF_GROUP_PARTS * (int64_t)FAR_REC, used, tcx, tcy, sm);
+                                         a.ff_top + t * FF_TOP_PARTS * (int64_t)FAR_REC, FF_TOP_PARTS, tcx, tcy, sm);
 }
 
 // Far-field mode, level 1: one block per super-patch, candidates from its group,
@@ -414,7 +422,7 @@ __global__ __launch_bounds__(FAR_THREADS) void farfield_super_group_kernel(const
     const int64_t sp = blockIdx.x;
     const int64_t g = group_of(a, sp);
     int64_t n;
-    const ListCandidates c = group_candidates(a, g, n);
+    const ListCandidates<FF_GROUP_PARTS> c = group_candidates(a, g, n);
     double cx, cy, H;
     super_geometry(a, sp, cx, cy, H);
     build_level<UNIT>(a, cx, cy, H, n, c, a.ff_near + sp * (int64_t)(1 + a.ff_cap), a.ff_cap,
@@ -845,7 +853,7 @@ hipError_t launch_farfield(const ShootArgs &a, hipStream_t stream) {
     if (a.ff_top) {
         const int64_t n_gy = (((nby + FF_SP_Y - 1) / FF_SP_Y) + FF_GROUP - 1) / FF_GROUP;
         const int64_t n_top = a.ff_tbx * ((n_gy + FF_TOP - 1) / FF_TOP);
-        const dim3 top_grid((unsigned)(n_top * group_parts(a.n_lens)));
+        const dim3 top_grid((unsigned)(n_top * FF_TOP_PARTS));
         if (unit) hipLaunchKernelGGL((farfield_top_kernel<true>), top_grid, dim3(FAR_TOP_THREADS), 0, stream, a);
         else hipLaunchKernelGGL((farfield_top_kernel<false>), top_grid, dim3(FAR_TOP_THREADS), 0, stream, a);
         if (unit) hipLaunchKernelGGL((farfield_group_top_kernel<true>), dim3((unsigned)n_group), group_block, 0, stream, a);

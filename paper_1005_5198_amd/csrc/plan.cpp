@@ -102,9 +102,9 @@ Plan make_plan(const rs_map_params *p, int64_t n_lens, int64_t rows_override) {
                 const int64_t gbx = (sbx + FF_GROUP - 1) / FF_GROUP, gby = (sby + FF_GROUP - 1) / FF_GROUP;
                 pl.top_cap = ((gbx + FF_TOP - 1) / FF_TOP) * ((gby + FF_TOP - 1) / FF_TOP);
                 pl.ff_top_off = off;
-                off += a256(sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.top_cap);
+                off += a256(sizeof(double) * FF_REC_DOUBLES * FF_TOP_PARTS * (size_t)pl.top_cap);
                 pl.ff_tlist_off = off;
-                off += a256(sizeof(int32_t) * (1 + (size_t)FF_TOP_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.top_cap);
+                off += a256(sizeof(int32_t) * (1 + (size_t)FF_TOP_PART_CAP) * FF_TOP_PARTS * (size_t)pl.top_cap);
             }
         }
         pl.bytes = off;

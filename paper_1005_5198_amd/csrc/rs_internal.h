@@ -71,8 +71,8 @@ struct ShootArgs {
     int32_t *ff_glist;     // far-field mode: [groups][FF_GROUP_PARTS][1 + FF_PART_CAP] count, then the nearer lenses
                            // (with tops: one list of FF_GROUP_ONE_CAP per group in the same place)
     int64_t ff_tbx;        // far-field mode with tops: tops (FF_TOP x FF_TOP groups) along x
-    double *ff_top;        // [tops][FF_GROUP_PARTS][FF_REC_DOUBLES] top records, per part, or nullptr (no tops)
-    int32_t *ff_tlist;     // [tops][FF_GROUP_PARTS][1 + FF_TOP_PART_CAP] count, then the nearer lenses
+    double *ff_top;        // [tops][FF_TOP_PARTS][FF_REC_DOUBLES] top records, per part, or nullptr (no tops)
+    int32_t *ff_tlist;     // [tops][FF_TOP_PARTS][1 + FF_TOP_PART_CAP] count, then the nearer lenses
 };
 
 

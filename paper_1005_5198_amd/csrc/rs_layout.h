@@ -49,12 +49,14 @@ constexpr int FF_GROUP_PARTS = 4;
 constexpr int FF_GROUP_CAP = 16384;
 constexpr int FF_PART_CAP = FF_GROUP_CAP / FF_GROUP_PARTS;
 // Far-field mode with at least FF_TOP_MIN_LENSES lenses: tops of FF_TOP x FF_TOP groups above
-// the groups. A top's lenses are scanned as a group's were (FF_GROUP_PARTS blocks, a record and
-// a list of capacity FF_TOP_PART_CAP each); a group then scans its top's lists instead of every
-// lens and keeps one list of capacity FF_GROUP_ONE_CAP in its lists' place.
+// the groups. A top's lenses are scanned as a group's were, by FF_TOP_PARTS blocks (a launch
+// holds few tops), each with a record and a list of capacity FF_TOP_PART_CAP; a group then
+// scans its top's lists instead of every lens and keeps one list of capacity FF_GROUP_ONE_CAP
+// in its lists' place.
 constexpr int FF_TOP = 4;
 constexpr int64_t FF_TOP_MIN_LENSES = 131072;
-constexpr int FF_TOP_PART_CAP = 32768;
+constexpr int FF_TOP_PARTS = 8;
+constexpr int FF_TOP_PART_CAP = 16384;
 constexpr int FF_GROUP_ONE_CAP = FF_GROUP_PARTS * (1 + FF_PART_CAP) - 1;
 // Far-field mode, per 64 x 32-ray patch: the local expansion about the patch
 // centre (16 real, 16 imaginary coefficients), the bound terms SFAR, far_err and

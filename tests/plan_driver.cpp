@@ -95,9 +95,9 @@ std::string check(const rs_map_params &p, int64_t n_lens, const Plan &pl) {
             if (pl.top_cap > 0) {
                 if (pl.top_cap < tops) return "too few top records";
                 if (pl.ff_top_off % 256 || pl.ff_top_off < end) return "top record offset";
-                end = pl.ff_top_off + sizeof(double) * FF_REC_DOUBLES * FF_GROUP_PARTS * (size_t)pl.top_cap;
+                end = pl.ff_top_off + sizeof(double) * FF_REC_DOUBLES * FF_TOP_PARTS * (size_t)pl.top_cap;
                 if (pl.ff_tlist_off % 256 || pl.ff_tlist_off < end) return "top list offset";
-                end = pl.ff_tlist_off + sizeof(int32_t) * (1 + (size_t)FF_TOP_PART_CAP) * FF_GROUP_PARTS * (size_t)pl.top_cap;
+                end = pl.ff_tlist_off + sizeof(int32_t) * (1 + (size_t)FF_TOP_PART_CAP) * FF_TOP_PARTS * (size_t)pl.top_cap;
                 if (end > pl.bytes) return "top lists beyond the workspace";
             }
         } else if (pl.top_cap != 0) {

@@ -116,7 +116,7 @@ def test_farfield_tops(rs):
 
 def test_farfield_top_list_overflows(rs):
     """140000 lenses of masses +1 and -1 in a disc of radius 40: every lens lies within four
-    half-diagonals of the window's top, so its four part lists (35000 lenses each) overflow and
+    half-diagonals of the window's top, so its eight part lists (17500 lenses each) overflow and
     the group scans every lens against the top's test; the group's list and the levels below
     overflow in turn."""
     rng = np.random.default_rng(26)
